@@ -1,0 +1,7 @@
+"""Seeded synthetic inputs (meshes, initial and boundary data) for line-DG.
+
+Shared by the CPU oracle, the tests and the benchmark; holds none of the
+discretisation's arithmetic.
+"""
+from .mesh import Mesh, gll_points, quad_mesh, hex_mesh, reorient_elements, line_end_node  # noqa: F401
+from . import fields, configs  # noqa: F401
