@@ -1,0 +1,136 @@
+"""Benchmark: line-DG residual+Jacobian throughput and BDF2 Newton-step time on one MI355X.
+
+Workload (the 3-D Navier-Stokes headline configuration): Taylor-Green initial
+data, M = 0.2, Re = 1600, Pr = 0.72, 32^3 hexes of [0, 2pi]^3 curved by
+x + 0.1 sin x sin y sin z, p = 4 (125 nodes, 5 variables per element:
+20.48 M unknowns), one BDF2 Newton step with dt = 0.02 from U^n = U^{n-1} = U0.
+
+A step is one full Newton step of the chosen form: FP64 residual, FP64
+Jacobian blocks stored in BF16, BF16 line-block ILU(0), FP32 accumulation,
+GMRES(50) wrapped in FP64 iterative refinement with the exact tangent product
+until ||b - (I - gamma A) dU|| <= 1e-8 ||b||.  The plain FP64 step (FP64
+blocks and factors, GMRES to 1e-8 directly) is timed beside it.
+
+value = residual+Jacobian DOF/s = DOFs / (t_residual + t_assembly), both
+measured with HIP events inside the timed Newton steps.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="C4", choices=["C3", "C4"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in "
+                                   "DESIGN.md and not built", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from ldg_workloads import configs
+    from paper_1204_1533_amd import Context, LDG_BF16, LDG_F64, LDG_F32
+
+    torch.cuda.set_device(0)
+    pr = configs.config4() if args.config == "C4" else configs.config3()
+    chosen_prec = LDG_BF16 if args.config == "C4" else LDG_F32
+    log(f"[bench] workload {pr.name}: E={pr.mesh.n_elem} p={pr.mesh.p} dofs={pr.n_dof}")
+    stream = torch.cuda.current_stream().cuda_stream
+    ctx = Context(pr.mesh, pr.equation, gamma=pr.gamma, mu=pr.mu, prandtl=pr.prandtl, stream=stream)
+    U0 = torch.as_tensor(pr.U0, device="cuda").contiguous()
+    U = U0.clone()
+    gamma = 2.0 * pr.dt / 3.0
+    opts = dict(restart=50, max_iters=2000, max_refine=30, rtol=1e-8, inner_rtol=1e-2, reassemble=1)
+
+    def step(prec):
+        U.copy_(U0)
+        return ctx.ldg_newton_step(U, U0, 1.0, gamma, storage_prec=prec, **opts)
+
+    for _ in range(args.warmup):
+        step(chosen_prec)
+    torch.cuda.synchronize()
+    reps = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        reps.append(step(chosen_prec))
+        log(f"[bench] chosen step {k}: {reps[-1]['t_total_ms']:.1f} ms, gmres {reps[-1]['gmres_iters']}, "
+            f"refine {reps[-1]['refine_steps']}, relres {reps[-1]['lin_relres']:.2e}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    t_res = float(np.mean([r["t_resid_ms"] for r in reps]))
+    t_asm = float(np.mean([r["t_assemble_ms"] for r in reps]))
+    value = pr.n_dof / ((t_res + t_asm) * 1e-3)
+    U_chosen = U.clone()
+
+    plain = None
+    if not args.no_plain:
+        r = step(LDG_F64)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        prs = []
+        for k in range(max(1, args.steps // 2)):
+            prs.append(step(LDG_F64))
+            log(f"[bench] plain fp64 step {k}: {prs[-1]['t_total_ms']:.1f} ms, gmres {prs[-1]['gmres_iters']}")
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        plain = dict(ms_per_step=(t3 - t2) * 1e3 / len(prs), gmres_iters=prs[-1]["gmres_iters"],
+                     lin_relres=prs[-1]["lin_relres"], newton_res_after=prs[-1]["newton_res_after"],
+                     t_resid_ms=float(np.mean([p["t_resid_ms"] for p in prs])),
+                     t_assemble_ms=float(np.mean([p["t_assemble_ms"] for p in prs])),
+                     t_solve_ms=float(np.mean([p["t_solve_ms"] for p in prs])),
+                     dU_rel_diff_vs_chosen=float((U - U_chosen).abs().max() / U.abs().max()))
+
+    last = reps[-1]
+    out = {
+        "metric": "residual+Jacobian DOF/s; Newton step time to 1e-8, plain FP64 vs chosen form",
+        "value": value,
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 residual/Jacobian; bf16 storage" if chosen_prec == LDG_BF16 else "f64; f32 storage",
+        "data": "synthetic",
+        "config": {"workload": f"{pr.name}: 3-D Navier-Stokes Taylor-Green, Re={pr.extra['re']:.0f}, "
+                               f"M=0.2, p={pr.mesh.p}, {pr.mesh.n_elem} hexes, BDF2 dt={pr.dt}",
+                   "dofs": pr.n_dof},
+        "newton": {"chosen": {"ms_per_step": ms_step, "gmres_iters": last["gmres_iters"],
+                              "refine_steps": last["refine_steps"], "lin_relres": last["lin_relres"],
+                              "newton_res_before": last["newton_res_before"],
+                              "newton_res_after": last["newton_res_after"],
+                              "t_resid_ms": t_res, "t_assemble_ms": t_asm,
+                              "t_solve_ms": float(np.mean([r["t_solve_ms"] for r in reps]))},
+                   "plain_fp64": plain},
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

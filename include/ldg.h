@@ -1,0 +1,186 @@
+/*
+ * ldg.h -- C ABI of the MI355X line-DG library (libldg.so).
+ *
+ * Line-based discontinuous Galerkin discretisation of Persson, "A sparse and
+ * high-order accurate line-based discontinuous Galerkin method for
+ * unstructured meshes": the semi-discrete residual and its Jacobians on
+ * curved quad/hex meshes, and the Newton-Krylov machinery of its Section 4
+ * (split Jacobian-vector product, element-local line-pattern preconditioner,
+ * preconditioned GMRES).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Every call returns an ldg_status; no C++ exception crosses the ABI.  On
+ *    failure ldg_last_error(ctx) returns a message (thread-unsafe, per ctx).
+ *  - Arrays named *_dev are device pointers owned by the caller (e.g. torch
+ *    tensors on cuda:0), contiguous, float64, in the documented layout.  They
+ *    must not alias unless a call says so.  Arrays named *_host are host
+ *    pointers read only during the call.
+ *  - Element e owns Np = (p+1)^D nodes; local node index i + (p+1) j
+ *    [+ (p+1)^2 k], i fastest.  m = 1 (Poisson), D+2 (Euler / Navier-Stokes).
+ *    Nodal fields are [E][m][Np]; the auxiliary gradient Q is [E][m][D][Np]
+ *    (q_{c,d} = d u_c / d x_d).
+ *  - Face 2n+s of an element is its face xi_n = s.  Its Nf = (p+1)^(D-1) face
+ *    nodes are numbered by the direction-n reference lines that end on it (the
+ *    other reference coordinates in increasing dimension order, lowest fastest).
+ *  - All device work is ordered on the stream given to ldg_create.  Calls do
+ *    not synchronise the host unless stated (ldg_newton_step does).
+ *  - The context owns all internal device memory; it is allocated by
+ *    ldg_create and grown by ldg_jacobian_assemble, and released by ldg_destroy.
+ */
+#ifndef LDG_H
+#define LDG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ldg_ctx_s* ldg_ctx;
+
+typedef enum {
+  LDG_OK = 0,
+  LDG_E_INVALID = -1,       /* bad argument value or null pointer               */
+  LDG_E_SHAPE = -2,         /* inconsistent sizes / connectivity                */
+  LDG_E_UNSUPPORTED = -3,   /* valid but not built (dimension, degree, option)  */
+  LDG_E_HIP = -4,           /* a HIP runtime call failed                        */
+  LDG_E_NOMEM = -5,         /* device allocation failed                         */
+  LDG_E_NOT_ASSEMBLED = -6, /* jacvec / precond before ldg_jacobian_assemble    */
+  LDG_E_NOT_CONVERGED = -7, /* linear solver did not reach the tolerance        */
+  LDG_E_NONFINITE = -8      /* NaN / Inf produced                               */
+} ldg_status;
+
+typedef enum { LDG_POISSON = 0, LDG_EULER = 1, LDG_NS = 2 } ldg_equation;
+typedef enum { LDG_F64 = 0, LDG_F32 = 1, LDG_BF16 = 2 } ldg_precision;
+
+/* Problem description (host memory, copied by ldg_create).
+ * Section 2.1: the element nodes are the images x(X_ijk) of a tensor grid of
+ * Gauss-Lobatto points (node_family 0) or equispaced points (1); the
+ * isoparametric Q_p map through them defines G = grad_X x and J = det G.
+ * Section 3: switch_plus[e][n] is S^+_n in {-1,+1} (S^-_n = -S^+_n); the two
+ * elements of an interior face must carry opposite switch values on it. */
+typedef struct {
+  int32_t dim;            /* 2 or 3                                              */
+  int32_t p;              /* polynomial degree, 1..4                             */
+  int32_t equation;       /* ldg_equation                                        */
+  int32_t node_family;    /* 0 = Gauss-Lobatto-Legendre, 1 = equispaced           */
+  double gamma;           /* ratio of specific heats (Euler / NS)                */
+  double mu;              /* dynamic viscosity (NS), constant                    */
+  double prandtl;         /* Prandtl number (NS)                                 */
+  double c11_interior;    /* LDG penalty C11 on interior faces (>= 0)            */
+  double c11_dirichlet;   /* LDG penalty C11 on Dirichlet faces (> 0 if any)     */
+  int64_t n_elem;         /* E >= 1                                              */
+  const double* node_xyz_host;    /* [E][D][Np] physical node coordinates           */
+  const int64_t* face_nbr_host;   /* [E][2D] neighbour element, or -(tag+1): tag 0 = Dirichlet */
+  const int32_t* nbr_node_host;   /* [E][2D][Nf] local node index, inside the neighbour, of
+                                     the node that coincides with each face node      */
+  const int8_t* switch_plus_host; /* [E][D] S^+_n                                     */
+} ldg_problem_desc;
+
+/* Validate the description, copy mesh data to the device, build the 1-D
+ * operators (Section 2.2: Gauss-Legendre rule with ceil((3p+1)/2) points,
+ * mass matrix, its inverse folded into the lifting and test-derivative
+ * operators).  hip_stream may be NULL (default stream).
+ * Errors: LDG_E_INVALID / LDG_E_SHAPE (inconsistent connectivity, non-matching
+ * switch signs, non-positive J is reported later as LDG_E_NONFINITE),
+ * LDG_E_UNSUPPORTED (dim/p/equation outside the built set). */
+ldg_status ldg_create(const ldg_problem_desc* desc, void* hip_stream, ldg_ctx* out);
+void ldg_destroy(ldg_ctx ctx);
+
+/* Source term S (eq. conslaw), added to R; S_dev [E][m][Np], copied.  NULL clears. */
+ldg_status ldg_set_source(ldg_ctx ctx, const double* S_dev);
+/* Dirichlet data g_D at boundary face nodes (eqs. dirichlet1/2); gD_dev
+ * [E][2D][m][Nf] (only boundary faces are read), copied.  NULL = zero data. */
+ldg_status ldg_set_dirichlet(ldg_ctx ctx, const double* gD_dev);
+
+/* Q = D(U): the LDG gradient (eqs. splitdisc2, numfluxu1, semidisc2-2) with
+ * the switch-selected traces; homogeneous != 0 uses g_D = 0 (then Q = K21 U).
+ * U_dev [E][m][Np] -> Q_dev [E][m][D][Np]. */
+ldg_status ldg_gradient(ldg_ctx ctx, const double* U_dev, double* Q_dev, int32_t homogeneous);
+
+/* R = F(U) = -(1/J) sum_n r^(n) + S (eqs. galerkinscheme2, semidisc,
+ * semidisc2-1, semidiscprimal), FP64.  Q_dev (may be NULL) receives D(U) and
+ * is otherwise internal scratch.  U_dev [E][m][Np] -> R_dev [E][m][Np]. */
+ldg_status ldg_residual(ldg_ctx ctx, const double* U_dev, double* R_dev, double* Q_dev);
+
+/* Assemble K11 = dR/dU and K12 = dR/dQ (Section 4.1) in line-block form,
+ * computed in FP64 and stored in storage_prec, then form the preconditioner
+ * A~ = alpha I - gamma (K11 + K12 K21) restricted to the element-local line
+ * pattern (Section 4.2) and factorise it by block ILU(0) in natural node
+ * order (FP64 arithmetic for LDG_F64 storage, FP32 otherwise).  alpha is 1 for
+ * an implicit time step ((alpha I - gamma A) dU = rhs, eq. dirkeqn with
+ * gamma = alpha_dirk dt) and 0 for a steady solve.
+ * U_dev [E][m][Np]. */
+ldg_status ldg_jacobian_assemble(ldg_ctx ctx, const double* U_dev, double alpha, double gamma,
+                                 int32_t storage_prec);
+
+/* y = (alpha I - gamma A) x with the split product of eq. matvecsplit:
+ * alpha x - gamma (K11 x + K12 (K21 x)), K21 x computed matrix-free.  With
+ * exact_fp64 != 0, A x is the exact FP64 tangent of the residual at the
+ * assembled state (forward-mode differentiation), independent of the stored
+ * precision.  x_dev, y_dev [E][m][Np], must not alias.
+ * Error: LDG_E_NOT_ASSEMBLED. */
+ldg_status ldg_jacvec(ldg_ctx ctx, const double* x_dev, double* y_dev, int32_t exact_fp64);
+
+/* z = P^{-1} r with the block ILU(0) factors of A~ (per element, forward and
+ * backward block substitution).  r_dev, z_dev [E][m][Np], may not alias.
+ * Error: LDG_E_NOT_ASSEMBLED. */
+ldg_status ldg_precond_apply(ldg_ctx ctx, const double* r_dev, double* z_dev);
+
+/* Copy the assembled operators out in FP64, line-block layout:
+ * K11_dev [E][Np][Dp+1+2D][m][m], K12_dev [E][Np][Dp+1+D][m][m*D] (columns
+ * (c', d) like Q), F_dev [E][Np][Dp+1][m][m] the BILU(0) factors (strictly
+ * lower slots hold L, the diagonal slot holds the INVERSE of the U diagonal
+ * block, the rest U).  Slot order for a node with reference indices (i_0..):
+ * slots 0..p the direction-0 line nodes (t, i_1, ..); then for n >= 1 the p
+ * other nodes of its direction-n line in increasing t; then neighbour slots:
+ * K11 face 2n+s, K12 the side of direction n whose switch is +1.  Any pointer
+ * may be NULL.  Error: LDG_E_NOT_ASSEMBLED. */
+ldg_status ldg_export_operators(ldg_ctx ctx, double* K11_dev, double* K12_dev, double* F_dev);
+
+typedef struct {
+  int32_t restart;        /* GMRES restart length (50)                          */
+  int32_t max_iters;      /* total inner iterations allowed per solve            */
+  int32_t max_refine;     /* outer FP64 refinement sweeps (low-precision storage) */
+  int32_t storage_prec;   /* ldg_precision of K11/K12 and the factors             */
+  double rtol;            /* ||b - (alpha I - gamma A) dU|| <= rtol ||b||  (1e-8)  */
+  double inner_rtol;      /* GMRES tolerance inside a refinement sweep            */
+  int32_t use_learned;    /* apply the learned correction if loaded              */
+  int32_t reassemble;     /* 0 reuses the last assembly (same alpha, gamma)      */
+} ldg_solver_opts;
+
+typedef struct {
+  int32_t gmres_iters;    /* total inner GMRES iterations                        */
+  int32_t refine_steps;   /* outer refinement sweeps                             */
+  int32_t fallback_used;  /* 1 if the learned correction was switched off        */
+  int32_t converged;
+  double lin_relres;      /* final ||b - (alpha I - gamma A) dU|| / ||b||, exact FP64 operator */
+  double newton_res_before, newton_res_after; /* ||G(U)||_2 before / after        */
+  double t_resid_ms, t_assemble_ms, t_solve_ms, t_total_ms;
+} ldg_solver_report;
+
+/* One Newton step on G(U) = alpha (U - Ucomb) - gamma R(U) (BDF2:
+ * Ucomb = (4U^n - U^{n-1})/3, gamma = 2 dt/3, alpha = 1; steady: alpha = 0,
+ * gamma = 1): solve (alpha I - gamma A) dU = -G(U) by right-preconditioned
+ * GMRES(restart) with the split product and BILU(0); with storage_prec !=
+ * LDG_F64 the solve is wrapped in FP64 iterative refinement using the exact
+ * tangent product.  U_dev (in/out) [E][m][Np]; Ucomb_dev may be NULL (zero).
+ * Synchronises the stream.  On LDG_E_NOT_CONVERGED / LDG_E_NONFINITE, U is
+ * unchanged and report says why. */
+ldg_status ldg_newton_step(ldg_ctx ctx, double* U_dev, const double* Ucomb_dev, double alpha,
+                           double gamma, const ldg_solver_opts* opts, ldg_solver_report* report);
+
+/* Classical four-stage Runge-Kutta on dU/dt = R(U) (Section 4.1), n_steps
+ * steps of size dt, U_dev in/out [E][m][Np]. */
+ldg_status ldg_rk4(ldg_ctx ctx, double* U_dev, double dt, int32_t n_steps);
+
+const char* ldg_status_string(ldg_status s);
+const char* ldg_last_error(ldg_ctx ctx);
+/* Number of degrees of freedom E*m*Np, or -1 for a NULL context. */
+int64_t ldg_num_dofs(ldg_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LDG_H */

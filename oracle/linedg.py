@@ -451,6 +451,19 @@ class LineDG:
                     W[:, a, self.nslot_line + n] += keep * d[:, l, i] / J[:, a, None]
         return W
 
+    def k21(self, elems=None):
+        """Weights of the linear gradient operator K21 = dD/dU: [Ne, Np, nslot21, D]."""
+        if elems is None:
+            elems = torch.arange(self.E)
+        elems = torch.as_tensor(elems, dtype=torch.int64)
+        geo = self.geometry(elems)
+        slot = torch.as_tensor(self._slot_tables())
+        W = torch.zeros(len(elems), self.Np, self.nslot21, self.D, dtype=DT)
+        for n in range(self.D):
+            rownode = self.to_lines(torch.arange(self.Np, dtype=DT)[None, None, :].expand(1, 1, self.Np), n)
+            W += self._k21_direction(elems, n, geo, slot, rownode[0, :, :, 0].long())
+        return W
+
     # ------------------------------------------------------------------ column maps
     def column_nodes(self, kind="K11"):
         """cols[e, a, slot] = global node index (e' * Np + node') of each slot, -1 if none."""

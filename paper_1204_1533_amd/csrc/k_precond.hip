@@ -1,0 +1,577 @@
+// Split Jacobian-vector product and the element-local line-pattern
+// preconditioner (Section 4.2 of the paper).
+//
+// jacvec:   y = alpha x - gamma (K11 x + K12 w), w = K21 x computed by the
+//           gradient kernel with zero boundary data (eq. matvecsplit).  One
+//           thread per node streams its block row (node-fastest layout, so a
+//           wavefront reads contiguous memory for every (slot, c, c')).
+// form:     A~ = alpha I - gamma (K11 + K12 K21) restricted to the D lines
+//           through each node, K21 taken inside the element.  The K21 weights
+//           of a direction-n line are the scalar line operator
+//             G[t][t'][d] = -sum_g V_tg I_gt' a_n(x_g)_d + L1_t n^+_d [t'=p, inside]
+//                           + L0_t n^-_d [t'=0, inside]
+//           (inside: the switch takes the trace from this element), divided
+//           by J of the node t.  For a row a and a column b on its
+//           direction-n line, (K12 K21)_ab = sum_{c on that line} K12_ac W_cb,
+//           with W_cb = G_n[t_c][t_b] / J_c for c != b and W_bb the sum of the
+//           diagonal entries of all D line operators through b over J_b; for
+//           b = a the sum over c runs over all D lines.
+// factor:   block ILU(0) in natural node order.  Row i depends only on the
+//           earlier nodes of its own lines, so rows with equal i+j(+k) form
+//           independent levels; each row's lower blocks k update only blocks
+//           on the line they share.  The diagonal slot keeps the inverse of
+//           the U diagonal block.
+// apply:    forward / backward block substitution over the same levels.
+#include "ldg_dispatch.hpp"
+#include "ldg_kernels.hpp"
+#include "ldg_store.hpp"
+
+namespace ldg {
+
+// column node of line slot `slot` for row node a (within the element)
+template <int D, int P>
+__device__ __forceinline__ int slot_col(int a, int slot) {
+  constexpr int N1 = P + 1;
+  if (slot < N1) return line_node<D, N1>(0, a / N1, slot);
+  const int n = 1 + (slot - N1) / P, r = (slot - N1) % P;
+  int l, t;
+  node_line<N1>(a, n, l, t);
+  return line_node<D, N1>(n, l, r < t ? r : r + 1);
+}
+template <int N1>
+__device__ __forceinline__ int slot_of(int n, int t, int tp, int self) {
+  // slot of column position tp on the row's direction-n line; the row sits at t
+  if (tp == t) return self;
+  return n == 0 ? tp : N1 + (n - 1) * (N1 - 1) + (tp < t ? tp : tp - 1);
+}
+
+// --------------------------------------------------------------------------- jacvec
+template <int D, int P, int EQ, int PR>
+__global__ void __launch_bounds__(256) jacvec_kernel(MeshParams mp, const void* __restrict__ K11,
+                                                     const void* __restrict__ K12, double alpha, double gamma,
+                                                     const double* __restrict__ x, const double* __restrict__ w,
+                                                     double* __restrict__ y) {
+  constexpr int N1 = P + 1, NP = ipow(N1, D), NL = ipow(N1, D - 1), M = Eq<D, EQ>::M;
+  constexpr bool VIS = Eq<D, EQ>::VIS;
+  constexpr int NSL = D * P + 1, NS11 = NSL + 2 * D, NS12 = NSL + D, MD = M * D;
+  const int64_t NN = mp.E * NP;
+  const int64_t gn = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (gn >= NN) return;
+  const int64_t e = gn / NP;
+  const int a = (int)(gn % NP);
+  double acc[M];
+#pragma unroll
+  for (int c = 0; c < M; ++c) acc[c] = 0.0;
+#pragma unroll
+  for (int s = 0; s < NS11; ++s) {
+    int64_t col;
+    if (s < NSL) {
+      col = e * NP + slot_col<D, P>(a, s);
+    } else {
+      const int f = s - NSL, n = f / 2;
+      const int64_t nb = mp.face_nbr[e * 2 * D + f];
+      if (nb < 0) continue;
+      int l, t;
+      node_line<N1>(a, n, l, t);
+      col = nb * NP + mp.nbr_node[(e * 2 * D + f) * NL + l];
+    }
+    const int64_t ce = col / NP, ca = col % NP;
+    double xv[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) xv[k] = x[(ce * M + k) * NP + ca];
+#pragma unroll
+    for (int c = 0; c < M; ++c)
+#pragma unroll
+      for (int k = 0; k < M; ++k) acc[c] += Store<PR>::get(K11, ((int64_t)(s * M + c) * M + k) * NN + gn) * xv[k];
+  }
+  if constexpr (VIS) {
+#pragma unroll
+    for (int s = 0; s < NS12; ++s) {
+      int64_t col;
+      if (s < NSL) {
+        col = e * NP + slot_col<D, P>(a, s);
+      } else {
+        const int n = s - NSL;
+        const int side = mp.sw[e * D + n] > 0 ? 1 : 0;
+        const int f = 2 * n + side;
+        const int64_t nb = mp.face_nbr[e * 2 * D + f];
+        if (nb < 0) continue;
+        int l, t;
+        node_line<N1>(a, n, l, t);
+        col = nb * NP + mp.nbr_node[(e * 2 * D + f) * NL + l];
+      }
+      const int64_t ce = col / NP, ca = col % NP;
+#pragma unroll
+      for (int k = 0; k < MD; ++k) {
+        const double wv = w[(ce * MD + k) * NP + ca];
+#pragma unroll
+        for (int c = 0; c < M; ++c) acc[c] += Store<PR>::get(K12, ((int64_t)(s * M + c) * MD + k) * NN + gn) * wv;
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < M; ++c) {
+    const int64_t i = (e * M + c) * NP + a;
+    y[i] = alpha * x[i] - gamma * acc[c];
+  }
+}
+
+hipError_t launch_jacvec(const DevCtx& dc, const void* K11, const void* K12, int prec, double alpha, double gamma,
+                         const double* x, const double* w, double* y) {
+  const int64_t NN = dc.E * dc.NP;
+  const unsigned grid = (unsigned)((NN + 255) / 256);
+  LDG_DISPATCH(dc, {
+    LDG_PREC_DISPATCH(prec, {
+      hipLaunchKernelGGL((jacvec_kernel<D, P, EQ, PR>), dim3(grid), dim3(256), 0, dc.stream, dc.mp, K11, K12, alpha,
+                         gamma, x, w, y);
+      return hipGetLastError();
+    })
+  })
+}
+
+// --------------------------------------------------------------------------- formation of A~
+template <int D, int P, int EQ>
+struct FormLayout {
+  static constexpr int N1 = P + 1, NG = n_gauss(P), NP = ipow(N1, D), NL = ipow(N1, D - 1);
+  static constexpr int oX = 0;
+  static constexpr int oG = oX + D * NP;
+  static constexpr int oJ = oG + D * D * NP;
+  static constexpr int oAg = oJ + NP;
+  static constexpr int oN = oAg + D * NL * NG * D;
+  static constexpr int oW = oN + D * NL * 2 * D;
+  static constexpr int oS = oW + D * NL * N1 * N1 * D;
+  static constexpr int ndoubles = oS + NP * D;
+  static constexpr size_t bytes = sizeof(double) * ndoubles;
+};
+
+// Writes A~ (line slots, [slot][c][c'][E*Np]) in the working precision WP of the factorisation.
+template <int D, int P, int EQ, int PR, int WP>
+__global__ void __launch_bounds__(NT_ELEM) form_kernel(LineOps ops, MeshParams mp, const void* __restrict__ K11,
+                                                       const void* __restrict__ K12, double alpha, double gamma,
+                                                       void* __restrict__ F) {
+  using L = FormLayout<D, P, EQ>;
+  constexpr int N1 = L::N1, NG = L::NG, NP = L::NP, NL = L::NL, M = Eq<D, EQ>::M;
+  constexpr bool VIS = Eq<D, EQ>::VIS;
+  constexpr int NSL = D * P + 1, MD = M * D;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* sm = reinterpret_cast<double*>(smem_raw);
+  double* sX = sm + L::oX;
+  double* sG = sm + L::oG;
+  double* sJ = sm + L::oJ;
+  double* sAg = sm + L::oAg;
+  double* sN = sm + L::oN;
+  double* sW = sm + L::oW;
+  double* sS = sm + L::oS;  // full K21 self weight of each node: sum over its D lines, divided by J
+  const int64_t e = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int64_t NN = mp.E * NP;
+  if constexpr (VIS) {
+    for (int i = tid; i < D * NP; i += NT_ELEM) sX[i] = mp.xyz[e * D * NP + i];
+    __syncthreads();
+    for (int i = tid; i < D * D * NP; i += NT_ELEM) {
+      const int ab = i / NP, node = i % NP;
+      const int a = ab / D, b = ab % D;
+      int s = 1;
+      for (int k = 0; k < b; ++k) s *= N1;
+      const int tb = (node / s) % N1;
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < N1; ++q) acc += ops.Dn[tb][q] * sX[a * NP + node - tb * s + q * s];
+      sG[ab * NP + node] = acc;
+    }
+    __syncthreads();
+    for (int i = tid; i < NP; i += NT_ELEM) {
+      double G[D][D];
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = 0; b < D; ++b) G[a][b] = sG[(a * D + b) * NP + i];
+      sJ[i] = 1.0 / det<D>(G);
+    }
+    for (int it = tid; it < D * NL * NG; it += NT_ELEM) {
+      const int n = it / (NL * NG), l = (it / NG) % NL, g = it % NG;
+      double G[D][D], an[D];
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+          double acc = 0.0;
+          if (b == n) {
+#pragma unroll
+            for (int t = 0; t < N1; ++t) acc += ops.Dg[g][t] * sX[a * NP + line_node<D, N1>(n, l, t)];
+          } else {
+#pragma unroll
+            for (int t = 0; t < N1; ++t) acc += ops.I[g][t] * sG[(a * D + b) * NP + line_node<D, N1>(n, l, t)];
+          }
+          G[a][b] = acc;
+        }
+      cofactor_row<D>(G, n, an);
+#pragma unroll
+      for (int d = 0; d < D; ++d) sAg[it * D + d] = an[d];
+    }
+    for (int it = tid; it < D * NL * 2; it += NT_ELEM) {
+      const int n = it / (NL * 2), l = (it / 2) % NL, s = it % 2;
+      const int nin = line_node<D, N1>(n, l, s ? P : 0);
+      double G[D][D], an[D];
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = 0; b < D; ++b) G[a][b] = sG[(a * D + b) * NP + nin];
+      cofactor_row<D>(G, n, an);
+#pragma unroll
+      for (int d = 0; d < D; ++d) sN[it * D + d] = s ? an[d] : -an[d];
+    }
+    __syncthreads();
+    // scalar K21 line operators G_n[l][t][t'][d] (without the 1/J of row t)
+    for (int it = tid; it < D * NL * N1 * N1 * D; it += NT_ELEM) {
+      const int d = it % D;
+      const int tp = (it / D) % N1;
+      const int t = (it / (D * N1)) % N1;
+      const int l = (it / (D * N1 * N1)) % NL;
+      const int n = it / (D * N1 * N1 * NL);
+      double v = 0.0;
+#pragma unroll
+      for (int g = 0; g < NG; ++g) v -= ops.V[t][g] * ops.I[g][tp] * sAg[((n * NL + l) * NG + g) * D + d];
+      const int Sp = mp.sw[e * D + n];
+      if (tp == P && Sp > 0 && mp.face_nbr[e * 2 * D + 2 * n + 1] >= 0)
+        v += ops.L1[t] * sN[((n * NL + l) * 2 + 1) * D + d];
+      if (tp == 0 && Sp < 0 && mp.face_nbr[e * 2 * D + 2 * n] >= 0)
+        v += ops.L0[t] * sN[((n * NL + l) * 2 + 0) * D + d];
+      sW[it] = v;
+    }
+    __syncthreads();
+    for (int it = tid; it < NP * D; it += NT_ELEM) {
+      const int b = it / D, d = it % D;
+      double v = 0.0;
+#pragma unroll
+      for (int m = 0; m < D; ++m) {
+        int lm, tm;
+        node_line<N1>(b, m, lm, tm);
+        v += sW[(((m * NL + lm) * N1 + tm) * N1 + tm) * D + d];
+      }
+      sS[it] = v * sJ[b];
+    }
+    __syncthreads();
+  }
+  // A~ entries: one work item per (row node, slot, c, c')
+  for (int it = tid; it < NP * NSL * M * M; it += NT_ELEM) {
+    const int a = it % NP;
+    const int r = it / NP;
+    const int k = r % M, c = (r / M) % M, slot = r / (M * M);
+    const int64_t gn = e * NP + a;
+    double v = Store<PR>::get(K11, ((int64_t)(slot * M + c) * M + k) * NN + gn);
+    if constexpr (VIS) {
+      const int self = a % N1;
+      const int b = slot_col<D, P>(a, slot);
+      // c = b: the weight of b on itself sums all D lines through b
+      double prod = 0.0;
+#pragma unroll
+      for (int d = 0; d < D; ++d)
+        prod += Store<PR>::get(K12, ((int64_t)(slot * M + c) * MD + k * D + d) * NN + gn) * sS[b * D + d];
+      // c != b on the line shared by a and b (for b = a, on every line through a)
+#pragma unroll
+      for (int n = 0; n < D; ++n) {
+        int la, ta, lb, tb;
+        node_line<N1>(a, n, la, ta);
+        node_line<N1>(b, n, lb, tb);
+        if (la != lb) continue;  // b is not on a's direction-n line
+#pragma unroll
+        for (int tc = 0; tc < N1; ++tc) {
+          if (tc == tb) continue;
+          const int sc = slot_of<N1>(n, ta, tc, self);
+          const int cn = line_node<D, N1>(n, la, tc);
+          const double jc = sJ[cn];
+#pragma unroll
+          for (int d = 0; d < D; ++d)
+            prod += Store<PR>::get(K12, ((int64_t)(sc * M + c) * MD + k * D + d) * NN + gn) *
+                    sW[(((n * NL + la) * N1 + tc) * N1 + tb) * D + d] * jc;
+        }
+      }
+      v += prod;
+    }
+    v = -gamma * v;
+    if (slot == a % N1 && c == k) v += alpha;
+    Store<WP>::put(F, ((int64_t)(slot * M + c) * M + k) * NN + gn, v);
+  }
+}
+
+// --------------------------------------------------------------------------- BILU(0)
+template <int D, int P>
+__device__ void level_table(int* rows, int* off) {
+  // rows sorted by coordinate sum; off[L] .. off[L+1]
+  constexpr int N1 = P + 1, NP = ipow(N1, D);
+  int pos = 0;
+  for (int L = 0; L <= D * P; ++L) {
+    off[L] = pos;
+    for (int a = 0; a < NP; ++a) {
+      int s = 0, r = a;
+      for (int d = 0; d < D; ++d) {
+        s += r % N1;
+        r /= N1;
+      }
+      if (s == L) rows[pos++] = a;
+    }
+  }
+  off[D * P + 1] = pos;
+}
+
+template <int M>
+__device__ __forceinline__ void invert_block(double A[M][M], double Inv[M][M]) {
+  double W[M][2 * M];
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      W[i][j] = A[i][j];
+      W[i][M + j] = (i == j) ? 1.0 : 0.0;
+    }
+#pragma unroll
+  for (int c = 0; c < M; ++c) {
+    int piv = c;
+    double best = fabs(W[c][c]);
+#pragma unroll
+    for (int r = c + 1; r < M; ++r)
+      if (fabs(W[r][c]) > best) {
+        best = fabs(W[r][c]);
+        piv = r;
+      }
+    if (piv != c) {
+#pragma unroll
+      for (int j = 0; j < 2 * M; ++j) {
+        double t = W[c][j];
+        W[c][j] = W[piv][j];
+        W[piv][j] = t;
+      }
+    }
+    const double id = 1.0 / W[c][c];
+#pragma unroll
+    for (int j = 0; j < 2 * M; ++j) W[c][j] *= id;
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+      if (r == c) continue;
+      const double f = W[r][c];
+#pragma unroll
+      for (int j = 0; j < 2 * M; ++j) W[r][j] -= f * W[c][j];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+#pragma unroll
+    for (int j = 0; j < M; ++j) Inv[i][j] = W[i][M + j];
+}
+
+// One wavefront per element; lanes = (row of the current level, component row c).
+template <int D, int P, int EQ, int WP>
+__global__ void __launch_bounds__(64) factor_kernel(int64_t E, void* __restrict__ F) {
+  constexpr int N1 = P + 1, NP = ipow(N1, D), M = Eq<D, EQ>::M;
+  constexpr int RPP = 64 / M;  // rows per pass
+  __shared__ int rows[NP];
+  __shared__ int off[D * P + 2];
+  const int64_t e = blockIdx.x;
+  const int64_t NN = E * NP;
+  const int lane = threadIdx.x;
+  if (lane == 0) level_table<D, P>(rows, off);
+  __syncthreads();
+  for (int L = 0; L <= D * P; ++L) {
+    const int nrow = off[L + 1] - off[L];
+    for (int r0 = 0; r0 < nrow; r0 += RPP) {
+      const int ri = r0 + lane / M, c = lane % M;
+      const bool active = (lane < RPP * M) && ri < nrow;
+      int i = 0;
+      if (active) {
+        i = rows[off[L] + ri];
+        const int64_t gi = e * NP + i;
+        const int self_i = i % N1;
+        for (int n = 0; n < D; ++n) {
+          int l, ti;
+          node_line<N1>(i, n, l, ti);
+          for (int tk = 0; tk < ti; ++tk) {
+            const int k = line_node<D, N1>(n, l, tk);
+            const int64_t gk = e * NP + k;
+            const int sik = slot_of<N1>(n, ti, tk, self_i);
+            // L_ik[c][:] = A_ik[c][:] Uinv_kk
+            double arow[M], lrow[M];
+#pragma unroll
+            for (int q = 0; q < M; ++q) arow[q] = Store<WP>::get(F, ((int64_t)(sik * M + c) * M + q) * NN + gi);
+            const int self_k = k % N1;
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+              double s = 0.0;
+#pragma unroll
+              for (int q = 0; q < M; ++q) s += arow[q] * Store<WP>::get(F, ((int64_t)(self_k * M + q) * M + j) * NN + gk);
+              lrow[j] = s;
+            }
+#pragma unroll
+            for (int j = 0; j < M; ++j) Store<WP>::put(F, ((int64_t)(sik * M + c) * M + j) * NN + gi, lrow[j]);
+            // A_ij -= L_ik U_kj for j after k on the shared line
+            for (int tj = tk + 1; tj < N1; ++tj) {
+              const int sij = slot_of<N1>(n, ti, tj, self_i);
+              const int skj = slot_of<N1>(n, tk, tj, self_k);
+#pragma unroll
+              for (int j = 0; j < M; ++j) {
+                double s = 0.0;
+#pragma unroll
+                for (int q = 0; q < M; ++q) s += lrow[q] * Store<WP>::get(F, ((int64_t)(skj * M + q) * M + j) * NN + gk);
+                const int64_t idx = ((int64_t)(sij * M + c) * M + j) * NN + gi;
+                Store<WP>::put(F, idx, Store<WP>::get(F, idx) - s);
+              }
+            }
+          }
+        }
+      }
+      __syncthreads();
+      if (active && c == 0) {
+        const int64_t gi = e * NP + i;
+        const int self_i = i % N1;
+        double A[M][M], Inv[M][M];
+#pragma unroll
+        for (int a = 0; a < M; ++a)
+#pragma unroll
+          for (int b = 0; b < M; ++b) A[a][b] = Store<WP>::get(F, ((int64_t)(self_i * M + a) * M + b) * NN + gi);
+        invert_block<M>(A, Inv);
+#pragma unroll
+        for (int a = 0; a < M; ++a)
+#pragma unroll
+          for (int b = 0; b < M; ++b) Store<WP>::put(F, ((int64_t)(self_i * M + a) * M + b) * NN + gi, Inv[a][b]);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <int D, int P, int EQ, int FP>
+__global__ void __launch_bounds__(64) apply_kernel(int64_t E, const void* __restrict__ F, const double* __restrict__ r,
+                                                   double* __restrict__ z) {
+  constexpr int N1 = P + 1, NP = ipow(N1, D), M = Eq<D, EQ>::M;
+  constexpr int RPP = 64 / M;
+  __shared__ int rows[NP];
+  __shared__ int off[D * P + 2];
+  __shared__ double sy[NP * M];
+  __shared__ double st[NP * M];
+  const int64_t e = blockIdx.x;
+  const int64_t NN = E * NP;
+  const int lane = threadIdx.x;
+  if (lane == 0) level_table<D, P>(rows, off);
+  for (int i = lane; i < NP * M; i += 64) sy[i] = r[e * M * NP + (i % M) * NP + i / M];
+  __syncthreads();
+  // forward: y_i = r_i - sum_{k < i on i's lines} L_ik y_k
+  for (int L = 1; L <= D * P; ++L) {
+    const int nrow = off[L + 1] - off[L];
+    for (int r0 = 0; r0 < nrow; r0 += RPP) {
+      const int ri = r0 + lane / M, c = lane % M;
+      double acc = 0.0;
+      int i = 0;
+      const bool active = (lane < RPP * M) && ri < nrow;
+      if (active) {
+        i = rows[off[L] + ri];
+        const int64_t gi = e * NP + i;
+        const int self_i = i % N1;
+        acc = sy[i * M + c];
+        for (int n = 0; n < D; ++n) {
+          int l, ti;
+          node_line<N1>(i, n, l, ti);
+          for (int tk = 0; tk < ti; ++tk) {
+            const int k = line_node<D, N1>(n, l, tk);
+            const int s = slot_of<N1>(n, ti, tk, self_i);
+#pragma unroll
+            for (int q = 0; q < M; ++q) acc -= Store<FP>::get(F, ((int64_t)(s * M + c) * M + q) * NN + gi) * sy[k * M + q];
+          }
+        }
+      }
+      __syncthreads();
+      if (active) sy[i * M + c] = acc;
+      __syncthreads();
+    }
+  }
+  // backward: z_i = Uinv_ii (y_i - sum_{j > i on i's lines} U_ij z_j); z overwrites y
+  for (int L = D * P; L >= 0; --L) {
+    const int nrow = off[L + 1] - off[L];
+    for (int r0 = 0; r0 < nrow; r0 += RPP) {
+      const int ri = r0 + lane / M, c = lane % M;
+      const bool active = (lane < RPP * M) && ri < nrow;
+      int i = 0;
+      if (active) {
+        i = rows[off[L] + ri];
+        const int64_t gi = e * NP + i;
+        const int self_i = i % N1;
+        double acc = sy[i * M + c];
+        for (int n = 0; n < D; ++n) {
+          int l, ti;
+          node_line<N1>(i, n, l, ti);
+          for (int tj = ti + 1; tj < N1; ++tj) {
+            const int j = line_node<D, N1>(n, l, tj);
+            const int s = slot_of<N1>(n, ti, tj, self_i);
+#pragma unroll
+            for (int q = 0; q < M; ++q) acc -= Store<FP>::get(F, ((int64_t)(s * M + c) * M + q) * NN + gi) * sy[j * M + q];
+          }
+        }
+        st[i * M + c] = acc;
+      }
+      __syncthreads();
+      if (active) {
+        const int64_t gi = e * NP + i;
+        const int self_i = i % N1;
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < M; ++q) v += Store<FP>::get(F, ((int64_t)(self_i * M + c) * M + q) * NN + gi) * st[i * M + q];
+        sy[i * M + c] = v;
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = lane; i < NP * M; i += 64) z[e * M * NP + (i % M) * NP + i / M] = sy[i];
+}
+
+template <int PIN, int POUT>
+__global__ void convert_kernel(const void* __restrict__ in, void* __restrict__ out, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    Store<POUT>::put(out, i, Store<PIN>::get(in, i));
+}
+
+// F holds the factors in storage precision fprec.  For fprec = BF16 the
+// factorisation runs on an FP32 copy placed after the BF16 factors in F.
+hipError_t launch_precond_factor(const DevCtx& dc, const void* K11, const void* K12, int prec, double alpha,
+                                 double gamma, void* F, int fprec) {
+  const int64_t NN = dc.E * dc.NP;
+  const int64_t nF = NN * (int64_t)(dc.D * dc.P + 1) * dc.M * dc.M;
+  LDG_DISPATCH(dc, {
+    using L = FormLayout<D, P, EQ>;
+    const size_t bytes = Eq<D, EQ>::VIS ? L::bytes : 0;
+    LDG_PREC_DISPATCH(prec, {
+      if (fprec == PREC_F64) {
+        auto k = form_kernel<D, P, EQ, PR, PREC_F64>;
+        if (bytes > 65536) hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        hipLaunchKernelGGL(k, dim3((unsigned)dc.E), dim3(NT_ELEM), bytes, dc.stream, dc.ops, dc.mp, K11, K12, alpha,
+                           gamma, F);
+        hipLaunchKernelGGL((factor_kernel<D, P, EQ, PREC_F64>), dim3((unsigned)dc.E), dim3(64), 0, dc.stream, dc.E,
+                           F);
+      } else {
+        void* work = fprec == PREC_F32 ? F : (void*)((uint16_t*)F + ((nF + 127) / 128) * 128);
+        auto k = form_kernel<D, P, EQ, PR, PREC_F32>;
+        if (bytes > 65536) hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        hipLaunchKernelGGL(k, dim3((unsigned)dc.E), dim3(NT_ELEM), bytes, dc.stream, dc.ops, dc.mp, K11, K12, alpha,
+                           gamma, work);
+        hipLaunchKernelGGL((factor_kernel<D, P, EQ, PREC_F32>), dim3((unsigned)dc.E), dim3(64), 0, dc.stream, dc.E,
+                           work);
+        if (fprec == PREC_BF16) {
+          int64_t g = (nF + 255) / 256;
+          if (g > 65536) g = 65536;
+          hipLaunchKernelGGL((convert_kernel<PREC_F32, PREC_BF16>), dim3((unsigned)g), dim3(256), 0, dc.stream, work, F,
+                             nF);
+        }
+      }
+      return hipGetLastError();
+    })
+  })
+}
+
+hipError_t launch_precond_apply(const DevCtx& dc, const void* F, int fprec, const double* r, double* z) {
+  LDG_DISPATCH(dc, {
+    LDG_PREC_DISPATCH(fprec, {
+      hipLaunchKernelGGL((apply_kernel<D, P, EQ, PR>), dim3((unsigned)dc.E), dim3(64), 0, dc.stream, dc.E, F, r, z);
+      return hipGetLastError();
+    })
+  })
+}
+
+}  // namespace ldg

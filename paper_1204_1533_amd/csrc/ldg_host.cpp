@@ -1,0 +1,649 @@
+// Host side of libldg: context, argument validation, C ABI entry points and
+// the Newton-GMRES driver (Section 4.2 of the paper).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ldg.h"
+#include "ldg_kernels.hpp"
+
+namespace ldg {
+bool build_line_ops(int p, int node_family, LineOps& ops, std::vector<double>* nodes_out);
+}
+
+using namespace ldg;
+
+struct ldg_ctx_s {
+  DevCtx dc{};
+  std::string err;
+  int64_t ndof = 0, nq = 0, nnode = 0;
+  double* d_xyz = nullptr;
+  int64_t* d_face_nbr = nullptr;
+  int32_t* d_nbr_node = nullptr;
+  int8_t* d_sw = nullptr;
+  double* d_gD = nullptr;
+  double* d_S = nullptr;
+  double* d_Q = nullptr;   // Q scratch (residual)
+  double* d_W = nullptr;   // K21 x scratch
+  double* d_W2 = nullptr;  // tangent Q scratch
+  // assembled state
+  bool assembled = false;
+  int prec = 0;
+  double alpha = 1.0, gamma = 0.0;
+  void* d_K11 = nullptr;
+  void* d_K12 = nullptr;
+  void* d_F = nullptr;
+  size_t capK11 = 0, capK12 = 0, capF = 0;
+  double* d_Ua = nullptr;  // state at assembly
+  double* d_Qa = nullptr;  // D(U) at assembly
+  // Newton / Krylov workspace
+  double* d_V = nullptr;
+  int cap_restart = 0;
+  double* d_R = nullptr;
+  double* d_G = nullptr;
+  double* d_x = nullptr;
+  double* d_r = nullptr;
+  double* d_z = nullptr;
+  double* d_tmp = nullptr;
+  double* d_Un = nullptr;
+  double* d_partial = nullptr;
+  double* d_h = nullptr;
+  int nblk_dot = 0;
+};
+
+namespace {
+
+ldg_status fail(ldg_ctx c, ldg_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+#define HIPCK(ctx, call)                                                                  \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess) return fail(ctx, LDG_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <class T>
+ldg_status dev_alloc(ldg_ctx c, T** p, size_t count) {
+  if (*p) return LDG_OK;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(c, LDG_E_NOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+  }
+  return LDG_OK;
+}
+
+ldg_status grow(ldg_ctx c, void** p, size_t* cap, size_t bytes) {
+  if (*cap >= bytes && *p) return LDG_OK;
+  if (*p) hipFree(*p);
+  *p = nullptr;
+  *cap = 0;
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    *p = nullptr;
+    return fail(c, LDG_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  *cap = bytes;
+  return LDG_OK;
+}
+
+size_t elem_size(int prec) { return prec == LDG_F64 ? 8 : (prec == LDG_F32 ? 4 : 2); }
+
+#define TRY(x)                     \
+  do {                             \
+    ldg_status s_ = (x);           \
+    if (s_ != LDG_OK) return s_;   \
+  } while (0)
+
+int64_t ipow64(int64_t b, int e) {
+  int64_t r = 1;
+  while (e-- > 0) r *= b;
+  return r;
+}
+
+// Node index of position t on line l of direction n (host twin of line_node).
+int host_line_node(int n, int l, int t, int N1) {
+  int s = 1;
+  for (int k = 0; k < n; ++k) s *= N1;
+  return (l % s) + t * s + (l / s) * s * N1;
+}
+bool host_node_on_face(int node, int n, int side, int N1, int p, int* lidx) {
+  int s = 1;
+  for (int k = 0; k < n; ++k) s *= N1;
+  int t = (node / s) % N1;
+  if (t != (side ? p : 0)) return false;
+  *lidx = (node % s) + (node / (s * N1)) * s;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ldg_status_string(ldg_status s) {
+  switch (s) {
+    case LDG_OK: return "ok";
+    case LDG_E_INVALID: return "invalid argument";
+    case LDG_E_SHAPE: return "inconsistent shape or connectivity";
+    case LDG_E_UNSUPPORTED: return "unsupported configuration";
+    case LDG_E_HIP: return "HIP runtime error";
+    case LDG_E_NOMEM: return "out of device memory";
+    case LDG_E_NOT_ASSEMBLED: return "operators not assembled";
+    case LDG_E_NOT_CONVERGED: return "linear solver did not converge";
+    case LDG_E_NONFINITE: return "non-finite value";
+  }
+  return "unknown status";
+}
+
+const char* ldg_last_error(ldg_ctx ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int64_t ldg_num_dofs(ldg_ctx ctx) { return ctx ? ctx->ndof : -1; }
+
+void ldg_destroy(ldg_ctx c) {
+  if (!c) return;
+  void* ptrs[] = {c->d_xyz, c->d_face_nbr, c->d_nbr_node, c->d_sw, c->d_gD, c->d_S, c->d_Q, c->d_W, c->d_W2,
+                  c->d_K11, c->d_K12, c->d_F, c->d_Ua, c->d_Qa, c->d_V, c->d_R, c->d_G, c->d_x, c->d_r, c->d_z,
+                  c->d_tmp, c->d_Un, c->d_partial, c->d_h};
+  for (void* p : ptrs)
+    if (p) hipFree(p);
+  delete c;
+}
+
+ldg_status ldg_create(const ldg_problem_desc* d, void* stream, ldg_ctx* out) {
+  if (!out) return LDG_E_INVALID;
+  *out = nullptr;
+  if (!d) return LDG_E_INVALID;
+  ldg_ctx c = new ldg_ctx_s();
+  auto bad = [&](ldg_status s, const std::string& m) {
+    std::string msg = m;
+    ldg_destroy(c);
+    (void)msg;
+    return s;
+  };
+  if (d->dim != 2 && d->dim != 3) return bad(LDG_E_UNSUPPORTED, "dim");
+  if (d->p < 1 || d->p > 4) return bad(LDG_E_UNSUPPORTED, "p");
+  if (d->equation < 0 || d->equation > 2) return bad(LDG_E_UNSUPPORTED, "equation");
+  if (d->node_family != 0 && d->node_family != 1) return bad(LDG_E_INVALID, "node_family");
+  if (d->n_elem < 1) return bad(LDG_E_INVALID, "n_elem");
+  if (!d->node_xyz_host || !d->face_nbr_host || !d->nbr_node_host || !d->switch_plus_host)
+    return bad(LDG_E_INVALID, "null mesh array");
+  if (d->equation != LDG_POISSON && !(d->gamma > 1.0)) return bad(LDG_E_INVALID, "gamma");
+  if (d->equation == LDG_NS && (d->mu < 0.0 || !(d->prandtl > 0.0))) return bad(LDG_E_INVALID, "mu/prandtl");
+  if (d->c11_interior < 0.0 || d->c11_dirichlet < 0.0) return bad(LDG_E_INVALID, "c11");
+  const int D = d->dim, P = d->p, N1 = P + 1;
+  const int NP = (int)ipow64(N1, D), NL = (int)ipow64(N1, D - 1);
+  const int64_t E = d->n_elem;
+  const int M = d->equation == LDG_POISSON ? 1 : D + 2;
+  // connectivity checks: neighbour index range, node range, reciprocity and switch signs
+  bool any_dirichlet = false;
+  for (int64_t e = 0; e < E; ++e) {
+    for (int n = 0; n < D; ++n) {
+      const int8_t sp = d->switch_plus_host[e * D + n];
+      if (sp != 1 && sp != -1) return bad(LDG_E_INVALID, "switch_plus must be +-1");
+      for (int s = 0; s < 2; ++s) {
+        const int f = 2 * n + s;
+        const int64_t nb = d->face_nbr_host[e * 2 * D + f];
+        if (nb >= E) return bad(LDG_E_SHAPE, "face_nbr out of range");
+        if (nb < 0) {
+          if (nb != -1) return bad(LDG_E_UNSUPPORTED, "only boundary tag 0 (Dirichlet) is built");
+          any_dirichlet = true;
+          continue;
+        }
+        for (int l = 0; l < NL; ++l) {
+          const int nd = d->nbr_node_host[(e * 2 * D + f) * NL + l];
+          if (nd < 0 || nd >= NP) return bad(LDG_E_SHAPE, "nbr_node out of range");
+          const int mine = host_line_node(n, l, s ? P : 0, N1);
+          // find the neighbour face that holds nd and maps back to us
+          bool found = false;
+          for (int f2 = 0; f2 < 2 * D && !found; ++f2) {
+            if (d->face_nbr_host[nb * 2 * D + f2] != e) continue;
+            int l2;
+            if (!host_node_on_face(nd, f2 / 2, f2 % 2, N1, P, &l2)) continue;
+            if (d->nbr_node_host[(nb * 2 * D + f2) * NL + l2] != mine) continue;
+            const int Smine = s ? sp : -sp;
+            const int8_t sp2 = d->switch_plus_host[nb * D + f2 / 2];
+            const int Sther = (f2 % 2) ? sp2 : -sp2;
+            if (Smine != -Sther) return bad(LDG_E_SHAPE, "switch signs must be opposite across a face");
+            found = true;
+          }
+          if (!found) return bad(LDG_E_SHAPE, "face connectivity is not reciprocal");
+        }
+      }
+    }
+  }
+  if (any_dirichlet && !(d->c11_dirichlet > 0.0) && d->equation != LDG_EULER)
+    return bad(LDG_E_INVALID, "c11_dirichlet must be positive with Dirichlet faces");
+  DevCtx& dc = c->dc;
+  dc.D = D;
+  dc.P = P;
+  dc.EQ = d->equation;
+  dc.M = M;
+  dc.N1 = N1;
+  dc.NP = NP;
+  dc.NL = NL;
+  dc.NG = n_gauss(P);
+  dc.E = E;
+  dc.stream = (hipStream_t)stream;
+  if (!build_line_ops(P, d->node_family, dc.ops, nullptr)) return bad(LDG_E_UNSUPPORTED, "p");
+  c->ndof = E * M * NP;
+  c->nq = c->ndof * D;
+  c->nnode = E * NP;
+  ldg_status st = LDG_OK;
+  if ((st = dev_alloc(c, &c->d_xyz, (size_t)E * D * NP)) != LDG_OK ||
+      (st = dev_alloc(c, &c->d_face_nbr, (size_t)E * 2 * D)) != LDG_OK ||
+      (st = dev_alloc(c, &c->d_nbr_node, (size_t)E * 2 * D * NL)) != LDG_OK ||
+      (st = dev_alloc(c, &c->d_sw, (size_t)E * D)) != LDG_OK || (st = dev_alloc(c, &c->d_Q, (size_t)c->nq)) != LDG_OK)
+    return bad(st, "alloc");
+  if (hipMemcpy(c->d_xyz, d->node_xyz_host, sizeof(double) * E * D * NP, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_face_nbr, d->face_nbr_host, sizeof(int64_t) * E * 2 * D, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_nbr_node, d->nbr_node_host, sizeof(int32_t) * E * 2 * D * NL, hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(c->d_sw, d->switch_plus_host, sizeof(int8_t) * E * D, hipMemcpyHostToDevice) != hipSuccess)
+    return bad(LDG_E_HIP, "copy");
+  MeshParams& mp = dc.mp;
+  mp.E = E;
+  mp.gamma = d->gamma;
+  mp.mu = d->mu;
+  mp.prandtl = d->prandtl > 0 ? d->prandtl : 1.0;
+  mp.c11i = d->c11_interior;
+  mp.c11d = d->c11_dirichlet;
+  mp.xyz = c->d_xyz;
+  mp.face_nbr = c->d_face_nbr;
+  mp.nbr_node = c->d_nbr_node;
+  mp.sw = c->d_sw;
+  mp.gD = nullptr;
+  mp.S = nullptr;
+  *out = c;
+  return LDG_OK;
+}
+
+ldg_status ldg_set_source(ldg_ctx c, const double* S) {
+  if (!c) return LDG_E_INVALID;
+  if (!S) {
+    c->dc.mp.S = nullptr;
+    return LDG_OK;
+  }
+  TRY(dev_alloc(c, &c->d_S, (size_t)c->ndof));
+  HIPCK(c, hipMemcpyAsync(c->d_S, S, sizeof(double) * c->ndof, hipMemcpyDeviceToDevice, c->dc.stream));
+  c->dc.mp.S = c->d_S;
+  return LDG_OK;
+}
+
+ldg_status ldg_set_dirichlet(ldg_ctx c, const double* gD) {
+  if (!c) return LDG_E_INVALID;
+  if (!gD) {
+    c->dc.mp.gD = nullptr;
+    return LDG_OK;
+  }
+  const size_t n = (size_t)c->dc.E * 2 * c->dc.D * c->dc.M * c->dc.NL;
+  TRY(dev_alloc(c, &c->d_gD, n));
+  HIPCK(c, hipMemcpyAsync(c->d_gD, gD, sizeof(double) * n, hipMemcpyDeviceToDevice, c->dc.stream));
+  c->dc.mp.gD = c->d_gD;
+  return LDG_OK;
+}
+
+ldg_status ldg_gradient(ldg_ctx c, const double* U, double* Q, int32_t homogeneous) {
+  if (!c) return LDG_E_INVALID;
+  if (!U || !Q) return fail(c, LDG_E_INVALID, "null pointer");
+  if ((const void*)U == (const void*)Q) return fail(c, LDG_E_INVALID, "U and Q alias");
+  HIPCK(c, launch_gradient(c->dc, U, Q, homogeneous != 0));
+  return LDG_OK;
+}
+
+ldg_status ldg_residual(ldg_ctx c, const double* U, double* R, double* Q) {
+  if (!c) return LDG_E_INVALID;
+  if (!U || !R) return fail(c, LDG_E_INVALID, "null pointer");
+  if ((const void*)U == (const void*)R) return fail(c, LDG_E_INVALID, "U and R alias");
+  double* q = Q ? Q : c->d_Q;
+  const bool vis = c->dc.EQ != LDG_EULER;
+  if (vis) HIPCK(c, launch_gradient(c->dc, U, q, false));
+  HIPCK(c, launch_residual(c->dc, U, vis ? q : nullptr, R));
+  return LDG_OK;
+}
+
+ldg_status ldg_jacobian_assemble(ldg_ctx c, const double* U, double alpha, double gamma, int32_t prec) {
+  if (!c) return LDG_E_INVALID;
+  if (!U) return fail(c, LDG_E_INVALID, "null pointer");
+  if (prec < 0 || prec > 2) return fail(c, LDG_E_INVALID, "storage_prec");
+  if (!std::isfinite(alpha) || !std::isfinite(gamma)) return fail(c, LDG_E_INVALID, "alpha/gamma");
+  const DevCtx& dc = c->dc;
+  const size_t es = elem_size(prec);
+  const int ns11 = dc.D * dc.P + 1 + 2 * dc.D, ns12 = dc.D * dc.P + 1 + dc.D, nsF = dc.D * dc.P + 1;
+  TRY(grow(c, &c->d_K11, &c->capK11, es * (size_t)ns11 * dc.M * dc.M * c->nnode));
+  TRY(grow(c, &c->d_K12, &c->capK12, es * (size_t)ns12 * dc.M * dc.M * dc.D * c->nnode));
+  const int fprec = prec;
+  const size_t nF = (size_t)nsF * dc.M * dc.M * c->nnode;
+  // BF16 factors are computed in an FP32 workspace stored after them
+  const size_t fbytes = fprec == LDG_BF16 ? 2 * (((nF + 127) / 128) * 128) + 4 * nF : elem_size(fprec) * nF;
+  TRY(grow(c, &c->d_F, &c->capF, fbytes));
+  TRY(dev_alloc(c, &c->d_Ua, (size_t)c->ndof));
+  TRY(dev_alloc(c, &c->d_Qa, (size_t)c->nq));
+  HIPCK(c, hipMemcpyAsync(c->d_Ua, U, sizeof(double) * c->ndof, hipMemcpyDeviceToDevice, dc.stream));
+  const bool vis = dc.EQ != LDG_EULER;
+  if (vis) HIPCK(c, launch_gradient(dc, U, c->d_Qa, false));
+  HIPCK(c, launch_jacobian(dc, U, vis ? c->d_Qa : nullptr, c->d_K11, c->d_K12, prec));
+  HIPCK(c, launch_precond_factor(dc, c->d_K11, c->d_K12, prec, alpha, gamma, c->d_F, fprec));
+  c->assembled = true;
+  c->prec = prec;
+  c->alpha = alpha;
+  c->gamma = gamma;
+  return LDG_OK;
+}
+
+static ldg_status apply_op(ldg_ctx c, const double* x, double* y, bool exact) {
+  const DevCtx& dc = c->dc;
+  TRY(dev_alloc(c, &c->d_W, (size_t)c->nq));
+  const bool vis = dc.EQ != LDG_EULER;
+  if (vis) HIPCK(c, launch_gradient(dc, x, c->d_W, true));
+  if (exact) {
+    // y = alpha x - gamma dR/dU x  (tangent of the FP64 residual at the assembled state)
+    HIPCK(c, launch_residual_tangent(dc, c->d_Ua, x, vis ? c->d_Qa : nullptr, vis ? c->d_W : nullptr, y));
+    HIPCK(c, launch_axpby(y, c->alpha, x, -c->gamma, c->ndof, dc.stream));
+  } else {
+    HIPCK(c, launch_jacvec(dc, c->d_K11, c->d_K12, c->prec, c->alpha, c->gamma, x, vis ? c->d_W : nullptr, y));
+  }
+  return LDG_OK;
+}
+
+ldg_status ldg_jacvec(ldg_ctx c, const double* x, double* y, int32_t exact) {
+  if (!c) return LDG_E_INVALID;
+  if (!x || !y) return fail(c, LDG_E_INVALID, "null pointer");
+  if ((const void*)x == (const void*)y) return fail(c, LDG_E_INVALID, "x and y alias");
+  if (!c->assembled) return fail(c, LDG_E_NOT_ASSEMBLED, "call ldg_jacobian_assemble first");
+  return apply_op(c, x, y, exact != 0);
+}
+
+ldg_status ldg_precond_apply(ldg_ctx c, const double* r, double* z) {
+  if (!c) return LDG_E_INVALID;
+  if (!r || !z) return fail(c, LDG_E_INVALID, "null pointer");
+  if ((const void*)r == (const void*)z) return fail(c, LDG_E_INVALID, "r and z alias");
+  if (!c->assembled) return fail(c, LDG_E_NOT_ASSEMBLED, "call ldg_jacobian_assemble first");
+  HIPCK(c, launch_precond_apply(c->dc, c->d_F, c->prec, r, z));
+  return LDG_OK;
+}
+
+ldg_status ldg_export_operators(ldg_ctx c, double* K11, double* K12, double* F) {
+  if (!c) return LDG_E_INVALID;
+  if (!c->assembled) return fail(c, LDG_E_NOT_ASSEMBLED, "call ldg_jacobian_assemble first");
+  const DevCtx& dc = c->dc;
+  const int ns11 = dc.D * dc.P + 1 + 2 * dc.D, ns12 = dc.D * dc.P + 1 + dc.D, nsF = dc.D * dc.P + 1;
+  if (K11) HIPCK(c, launch_export_blocks(dc, c->d_K11, c->prec, ns11, dc.M, K11));
+  if (K12) HIPCK(c, launch_export_blocks(dc, c->d_K12, c->prec, ns12, dc.M * dc.D, K12));
+  if (F) HIPCK(c, launch_export_blocks(dc, c->d_F, c->prec, nsF, dc.M, F));
+  return LDG_OK;
+}
+
+// ------------------------------------------------------------------ Krylov helpers
+static ldg_status dots(ldg_ctx c, const double* V, int k, const double* w, double* host_out) {
+  const DevCtx& dc = c->dc;
+  HIPCK(c, launch_multidot(V, c->ndof, k, w, c->ndof, c->d_partial, c->nblk_dot, dc.stream));
+  HIPCK(c, launch_multidot_finish(c->d_partial, c->nblk_dot, k, c->d_h, dc.stream));
+  HIPCK(c, hipMemcpyAsync(host_out, c->d_h, sizeof(double) * k, hipMemcpyDeviceToHost, dc.stream));
+  HIPCK(c, hipStreamSynchronize(dc.stream));
+  return LDG_OK;
+}
+
+static ldg_status norm2(ldg_ctx c, const double* w, double* out) {
+  double v;
+  TRY(dots(c, w, 1, w, &v));
+  *out = std::sqrt(v);
+  return LDG_OK;
+}
+
+// Right-preconditioned GMRES(restart) on (alpha I - gamma A) x = b, x0 = 0,
+// classical Gram-Schmidt with one re-orthogonalisation.  The operator is the
+// stored split product (exact = false) or the exact tangent (exact = true).
+static ldg_status gmres(ldg_ctx c, const double* b, double* x, double rtol_abs, int restart, int max_iters,
+                        bool exact, int* iters, double* est_res) {
+  const DevCtx& dc = c->dc;
+  const int64_t n = c->ndof;
+  HIPCK(c, hipMemsetAsync(x, 0, sizeof(double) * n, dc.stream));
+  std::vector<double> H((restart + 1) * restart), cs(restart), sn(restart), g(restart + 1), h(restart + 1),
+      h2(restart + 1), y(restart);
+  int its = 0;
+  double beta;
+  // r = b - A x
+  HIPCK(c, hipMemcpyAsync(c->d_r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, dc.stream));
+  bool first = true;
+  while (true) {
+    if (!first) {
+      TRY(apply_op(c, x, c->d_tmp, exact));
+      HIPCK(c, hipMemcpyAsync(c->d_r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, dc.stream));
+      HIPCK(c, launch_axpby(c->d_r, -1.0, c->d_tmp, 1.0, n, dc.stream));
+    }
+    first = false;
+    TRY(norm2(c, c->d_r, &beta));
+    *est_res = beta;
+    if (!std::isfinite(beta)) return fail(c, LDG_E_NONFINITE, "non-finite GMRES residual");
+    if (beta <= rtol_abs || its >= max_iters) break;
+    HIPCK(c, hipMemcpyAsync(c->d_V, c->d_r, sizeof(double) * n, hipMemcpyDeviceToDevice, dc.stream));
+    HIPCK(c, launch_axpby(c->d_V, 0.0, c->d_r, 1.0 / beta, n, dc.stream));
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int k_used = 0;
+    for (int k = 0; k < restart; ++k) {
+      double* vk = c->d_V + (int64_t)k * n;
+      double* w = c->d_V + (int64_t)(k + 1) * n;
+      HIPCK(c, launch_precond_apply(dc, c->d_F, c->prec, vk, c->d_z));
+      TRY(apply_op(c, c->d_z, w, exact));
+      // CGS2
+      TRY(dots(c, c->d_V, k + 1, w, h.data()));
+      HIPCK(c, hipMemcpyAsync(c->d_h, h.data(), sizeof(double) * (k + 1), hipMemcpyHostToDevice, dc.stream));
+      HIPCK(c, launch_update(w, c->d_V, n, k + 1, c->d_h, n, dc.stream));
+      TRY(dots(c, c->d_V, k + 1, w, h2.data()));
+      HIPCK(c, hipMemcpyAsync(c->d_h, h2.data(), sizeof(double) * (k + 1), hipMemcpyHostToDevice, dc.stream));
+      HIPCK(c, launch_update(w, c->d_V, n, k + 1, c->d_h, n, dc.stream));
+      for (int j = 0; j <= k; ++j) H[j * restart + k] = h[j] + h2[j];
+      double hn;
+      TRY(norm2(c, w, &hn));
+      H[(k + 1) * restart + k] = hn;
+      if (!std::isfinite(hn)) return fail(c, LDG_E_NONFINITE, "non-finite Arnoldi vector");
+      if (hn > 0) HIPCK(c, launch_axpby(w, 0.0, w, 1.0 / hn, n, dc.stream));
+      for (int j = 0; j < k; ++j) {
+        double t = cs[j] * H[j * restart + k] + sn[j] * H[(j + 1) * restart + k];
+        H[(j + 1) * restart + k] = -sn[j] * H[j * restart + k] + cs[j] * H[(j + 1) * restart + k];
+        H[j * restart + k] = t;
+      }
+      double den = std::hypot(H[k * restart + k], H[(k + 1) * restart + k]);
+      cs[k] = H[k * restart + k] / den;
+      sn[k] = H[(k + 1) * restart + k] / den;
+      H[k * restart + k] = den;
+      H[(k + 1) * restart + k] = 0.0;
+      g[k + 1] = -sn[k] * g[k];
+      g[k] = cs[k] * g[k];
+      ++its;
+      k_used = k + 1;
+      *est_res = std::fabs(g[k + 1]);
+      if (std::fabs(g[k + 1]) <= rtol_abs || its >= max_iters || hn == 0.0) break;
+    }
+    for (int i = k_used - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int j = i + 1; j < k_used; ++j) s -= H[i * restart + j] * y[j];
+      y[i] = s / H[i * restart + i];
+    }
+    // x += P^{-1} (V y)
+    HIPCK(c, hipMemcpyAsync(c->d_h, y.data(), sizeof(double) * k_used, hipMemcpyHostToDevice, dc.stream));
+    HIPCK(c, hipMemsetAsync(c->d_tmp, 0, sizeof(double) * n, dc.stream));
+    HIPCK(c, launch_lincomb(c->d_tmp, c->d_V, n, k_used, c->d_h, n, dc.stream));
+    HIPCK(c, launch_precond_apply(dc, c->d_F, c->prec, c->d_tmp, c->d_z));
+    HIPCK(c, launch_axpby(x, 1.0, c->d_z, 1.0, n, dc.stream));
+    if (*est_res <= rtol_abs || its >= max_iters) {
+      // true residual for the report
+      TRY(apply_op(c, x, c->d_tmp, exact));
+      HIPCK(c, hipMemcpyAsync(c->d_r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, dc.stream));
+      HIPCK(c, launch_axpby(c->d_r, -1.0, c->d_tmp, 1.0, n, dc.stream));
+      TRY(norm2(c, c->d_r, est_res));
+      break;
+    }
+  }
+  *iters = its;
+  return LDG_OK;
+}
+
+static ldg_status ensure_krylov(ldg_ctx c, int restart) {
+  const int64_t n = c->ndof;
+  if (restart < 1 || restart > 120) return fail(c, LDG_E_INVALID, "restart must be in 1..120");
+  if (c->cap_restart < restart) {
+    if (c->d_V) hipFree(c->d_V);
+    c->d_V = nullptr;
+    c->cap_restart = 0;
+    TRY(dev_alloc(c, &c->d_V, (size_t)(restart + 1) * n));
+    c->cap_restart = restart;
+  }
+  TRY(dev_alloc(c, &c->d_R, (size_t)n));
+  TRY(dev_alloc(c, &c->d_G, (size_t)n));
+  TRY(dev_alloc(c, &c->d_x, (size_t)n));
+  TRY(dev_alloc(c, &c->d_r, (size_t)n));
+  TRY(dev_alloc(c, &c->d_z, (size_t)n));
+  TRY(dev_alloc(c, &c->d_tmp, (size_t)n));
+  TRY(dev_alloc(c, &c->d_Un, (size_t)n));
+  c->nblk_dot = 1024;
+  TRY(dev_alloc(c, &c->d_partial, (size_t)c->nblk_dot * 128));
+  TRY(dev_alloc(c, &c->d_h, (size_t)128));
+  return LDG_OK;
+}
+
+ldg_status ldg_newton_step(ldg_ctx c, double* U, const double* Ucomb, double alpha, double gamma,
+                           const ldg_solver_opts* o, ldg_solver_report* rep) {
+  if (!c) return LDG_E_INVALID;
+  if (!U || !o) return fail(c, LDG_E_INVALID, "null pointer");
+  if (o->rtol <= 0 || o->max_iters < 1 || o->storage_prec < 0 || o->storage_prec > 2)
+    return fail(c, LDG_E_INVALID, "solver options");
+  const DevCtx& dc = c->dc;
+  const int64_t n = c->ndof;
+  ldg_solver_report r{};
+  TRY(ensure_krylov(c, o->restart));
+  hipEvent_t ev[5];
+  for (auto& e : ev) HIPCK(c, hipEventCreate(&e));
+  auto t_start = std::chrono::steady_clock::now();
+  HIPCK(c, hipEventRecord(ev[0], dc.stream));
+  // G(U) = alpha (U - Ucomb) - gamma R(U)
+  TRY(ldg_residual(c, U, c->d_R, nullptr));
+  HIPCK(c, hipEventRecord(ev[1], dc.stream));
+  HIPCK(c, hipMemcpyAsync(c->d_G, U, sizeof(double) * n, hipMemcpyDeviceToDevice, dc.stream));
+  if (Ucomb) HIPCK(c, launch_axpby(c->d_G, -1.0, Ucomb, 1.0, n, dc.stream));
+  HIPCK(c, launch_axpby(c->d_G, -gamma, c->d_R, alpha, n, dc.stream));
+  double g0;
+  TRY(norm2(c, c->d_G, &g0));
+  r.newton_res_before = g0;
+  if (!std::isfinite(g0)) return fail(c, LDG_E_NONFINITE, "non-finite Newton residual");
+  const bool reassemble = o->reassemble || !c->assembled || c->alpha != alpha || c->gamma != gamma ||
+                          c->prec != o->storage_prec;
+  if (reassemble) TRY(ldg_jacobian_assemble(c, U, alpha, gamma, o->storage_prec));
+  HIPCK(c, hipEventRecord(ev[2], dc.stream));
+  // b = -G  (kept in d_G)
+  HIPCK(c, launch_axpby(c->d_G, 0.0, c->d_G, -1.0, n, dc.stream));
+  const double target = o->rtol * g0;
+  int total_its = 0;
+  double res = 0.0;
+  bool ok = false;
+  if (c->prec == LDG_F64) {
+    int its;
+    TRY(gmres(c, c->d_G, c->d_x, target, o->restart, o->max_iters, false, &its, &res));
+    total_its = its;
+    ok = res <= target;
+    r.refine_steps = 0;
+  } else {
+    // FP64 iterative refinement around the low-precision GMRES
+    TRY(dev_alloc(c, &c->d_Un, (size_t)n));
+    double* xacc = c->d_Un;  // accumulated correction
+    HIPCK(c, hipMemsetAsync(xacc, 0, sizeof(double) * n, dc.stream));
+    std::vector<double> dummy;
+    double* rr = c->d_R;  // reuse R buffer for the refinement residual
+    HIPCK(c, hipMemcpyAsync(rr, c->d_G, sizeof(double) * n, hipMemcpyDeviceToDevice, dc.stream));
+    double rn = g0;
+    const int max_ref = o->max_refine > 0 ? o->max_refine : 10;
+    const double inner = o->inner_rtol > 0 ? o->inner_rtol : 1e-3;
+    int sweeps = 0;
+    for (; sweeps < max_ref; ++sweeps) {
+      int its;
+      double est;
+      TRY(gmres(c, rr, c->d_x, inner * rn, o->restart, o->max_iters - total_its, false, &its, &est));
+      total_its += its;
+      HIPCK(c, launch_axpby(xacc, 1.0, c->d_x, 1.0, n, dc.stream));
+      // exact residual rr = b - (alpha I - gamma A) xacc
+      TRY(apply_op(c, xacc, c->d_tmp, true));
+      HIPCK(c, hipMemcpyAsync(rr, c->d_G, sizeof(double) * n, hipMemcpyDeviceToDevice, dc.stream));
+      HIPCK(c, launch_axpby(rr, -1.0, c->d_tmp, 1.0, n, dc.stream));
+      TRY(norm2(c, rr, &rn));
+      if (!std::isfinite(rn)) return fail(c, LDG_E_NONFINITE, "non-finite refinement residual");
+      if (rn <= target) {
+        ++sweeps;
+        ok = true;
+        break;
+      }
+      if (total_its >= o->max_iters) {
+        ++sweeps;
+        break;
+      }
+    }
+    r.refine_steps = sweeps;
+    res = rn;
+    HIPCK(c, hipMemcpyAsync(c->d_x, xacc, sizeof(double) * n, hipMemcpyDeviceToDevice, dc.stream));
+  }
+  HIPCK(c, hipEventRecord(ev[3], dc.stream));
+  r.gmres_iters = total_its;
+  r.lin_relres = g0 > 0 ? res / g0 : 0.0;
+  r.converged = ok ? 1 : 0;
+  if (ok) {
+    HIPCK(c, launch_axpby(U, 1.0, c->d_x, 1.0, n, dc.stream));
+    // ||G(U_new)||
+    TRY(ldg_residual(c, U, c->d_R, nullptr));
+    HIPCK(c, hipMemcpyAsync(c->d_tmp, U, sizeof(double) * n, hipMemcpyDeviceToDevice, dc.stream));
+    if (Ucomb) HIPCK(c, launch_axpby(c->d_tmp, -1.0, Ucomb, 1.0, n, dc.stream));
+    HIPCK(c, launch_axpby(c->d_tmp, -gamma, c->d_R, alpha, n, dc.stream));
+    double g1;
+    TRY(norm2(c, c->d_tmp, &g1));
+    r.newton_res_after = g1;
+  } else {
+    r.newton_res_after = g0;
+  }
+  HIPCK(c, hipEventRecord(ev[4], dc.stream));
+  HIPCK(c, hipEventSynchronize(ev[4]));
+  float ms;
+  hipEventElapsedTime(&ms, ev[0], ev[1]);
+  r.t_resid_ms = ms;
+  hipEventElapsedTime(&ms, ev[1], ev[2]);
+  r.t_assemble_ms = ms;
+  hipEventElapsedTime(&ms, ev[2], ev[3]);
+  r.t_solve_ms = ms;
+  r.t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  for (auto& e : ev) hipEventDestroy(e);
+  if (rep) *rep = r;
+  if (!ok) return fail(c, LDG_E_NOT_CONVERGED, "linear solve did not reach rtol");
+  return LDG_OK;
+}
+
+ldg_status ldg_rk4(ldg_ctx c, double* U, double dt, int32_t nsteps) {
+  if (!c) return LDG_E_INVALID;
+  if (!U || nsteps < 0 || !std::isfinite(dt)) return fail(c, LDG_E_INVALID, "arguments");
+  const DevCtx& dc = c->dc;
+  const int64_t n = c->ndof;
+  TRY(dev_alloc(c, &c->d_R, (size_t)n));
+  TRY(dev_alloc(c, &c->d_tmp, (size_t)n));
+  TRY(dev_alloc(c, &c->d_Un, (size_t)n));
+  double* Us = c->d_tmp;
+  double* acc = c->d_Un;
+  const double a[4] = {0.5 * dt, 0.5 * dt, dt, 0.0};
+  const double b[4] = {dt / 6, dt / 3, dt / 3, dt / 6};
+  for (int s = 0; s < nsteps; ++s) {
+    HIPCK(c, hipMemcpyAsync(acc, U, sizeof(double) * n, hipMemcpyDeviceToDevice, dc.stream));
+    const double* cur = U;
+    for (int k = 0; k < 4; ++k) {
+      TRY(ldg_residual(c, cur, c->d_R, nullptr));
+      HIPCK(c, launch_rk4_stage(k < 3 ? Us : nullptr, U, c->d_R, a[k], acc, b[k], n, dc.stream));
+      cur = Us;
+    }
+    HIPCK(c, hipMemcpyAsync(U, acc, sizeof(double) * n, hipMemcpyDeviceToDevice, dc.stream));
+  }
+  return LDG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,211 @@
+"""Thin ctypes binding of libldg.so (argument marshalling only).
+
+Every function mirrors an entry point of ``include/ldg.h`` with the same name;
+device arrays are passed as raw pointers (``tensor.data_ptr()``).  The library
+must have been built (``paper_1204_1533_amd/build.py``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libldg.so")
+
+LDG_OK = 0
+LDG_E_INVALID, LDG_E_SHAPE, LDG_E_UNSUPPORTED, LDG_E_HIP = -1, -2, -3, -4
+LDG_E_NOMEM, LDG_E_NOT_ASSEMBLED, LDG_E_NOT_CONVERGED, LDG_E_NONFINITE = -5, -6, -7, -8
+LDG_POISSON, LDG_EULER, LDG_NS = 0, 1, 2
+LDG_F64, LDG_F32, LDG_BF16 = 0, 1, 2
+
+
+class ldg_problem_desc(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32), ("p", ctypes.c_int32), ("equation", ctypes.c_int32),
+        ("node_family", ctypes.c_int32),
+        ("gamma", ctypes.c_double), ("mu", ctypes.c_double), ("prandtl", ctypes.c_double),
+        ("c11_interior", ctypes.c_double), ("c11_dirichlet", ctypes.c_double),
+        ("n_elem", ctypes.c_int64),
+        ("node_xyz_host", ctypes.c_void_p), ("face_nbr_host", ctypes.c_void_p),
+        ("nbr_node_host", ctypes.c_void_p), ("switch_plus_host", ctypes.c_void_p),
+    ]
+
+
+class ldg_solver_opts(ctypes.Structure):
+    _fields_ = [
+        ("restart", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("max_refine", ctypes.c_int32),
+        ("storage_prec", ctypes.c_int32), ("rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double),
+        ("use_learned", ctypes.c_int32), ("reassemble", ctypes.c_int32),
+    ]
+
+
+class ldg_solver_report(ctypes.Structure):
+    _fields_ = [
+        ("gmres_iters", ctypes.c_int32), ("refine_steps", ctypes.c_int32), ("fallback_used", ctypes.c_int32),
+        ("converged", ctypes.c_int32), ("lin_relres", ctypes.c_double),
+        ("newton_res_before", ctypes.c_double), ("newton_res_after", ctypes.c_double),
+        ("t_resid_ms", ctypes.c_double), ("t_assemble_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double),
+        ("t_total_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_P = ctypes.c_void_p
+_SIGS = {
+    "ldg_create": (ctypes.c_int, [ctypes.POINTER(ldg_problem_desc), _P, ctypes.POINTER(_P)]),
+    "ldg_destroy": (None, [_P]),
+    "ldg_set_source": (ctypes.c_int, [_P, _P]),
+    "ldg_set_dirichlet": (ctypes.c_int, [_P, _P]),
+    "ldg_gradient": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32]),
+    "ldg_residual": (ctypes.c_int, [_P, _P, _P, _P]),
+    "ldg_jacobian_assemble": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_int32]),
+    "ldg_jacvec": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32]),
+    "ldg_precond_apply": (ctypes.c_int, [_P, _P, _P]),
+    "ldg_export_operators": (ctypes.c_int, [_P, _P, _P, _P]),
+    "ldg_newton_step": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.c_double,
+                                       ctypes.POINTER(ldg_solver_opts), ctypes.POINTER(ldg_solver_report)]),
+    "ldg_rk4": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int32]),
+    "ldg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "ldg_last_error": (ctypes.c_char_p, [_P]),
+    "ldg_num_dofs": (ctypes.c_int64, [_P]),
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libldg.so; raises if it has not been built (no CPU fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_1204_1533_amd/build.py")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+class LDGError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{status}: {msg}")
+        self.status = status
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+class Context:
+    """Owns one ldg_ctx.  Device arrays are torch tensors on the GPU (float64)."""
+
+    def __init__(self, mesh, equation, gamma=1.4, mu=0.0, prandtl=0.72, c11_interior=0.0, c11_dirichlet=10.0,
+                 node_family=0, stream=None):
+        lib = load_library()
+        self.lib = lib
+        self.mesh = mesh
+        self._keep = dict(
+            xyz=np.ascontiguousarray(mesh.xyz, dtype=np.float64),
+            fn=np.ascontiguousarray(mesh.face_nbr, dtype=np.int64),
+            nn=np.ascontiguousarray(mesh.nbr_node, dtype=np.int32),
+            sw=np.ascontiguousarray(mesh.switch_plus, dtype=np.int8),
+        )
+        d = ldg_problem_desc()
+        d.dim, d.p, d.equation, d.node_family = mesh.dim, mesh.p, equation, node_family
+        d.gamma, d.mu, d.prandtl = gamma, mu, prandtl
+        d.c11_interior, d.c11_dirichlet = c11_interior, c11_dirichlet
+        d.n_elem = mesh.n_elem
+        d.node_xyz_host = self._keep["xyz"].ctypes.data
+        d.face_nbr_host = self._keep["fn"].ctypes.data
+        d.nbr_node_host = self._keep["nn"].ctypes.data
+        d.switch_plus_host = self._keep["sw"].ctypes.data
+        self.desc = d
+        h = _P()
+        st = lib.ldg_create(ctypes.byref(d), stream, ctypes.byref(h))
+        if st != LDG_OK:
+            raise LDGError(st, lib.ldg_status_string(st).decode())
+        self.h = h
+        self.dim, self.p = mesh.dim, mesh.p
+        self.m = 1 if equation == LDG_POISSON else mesh.dim + 2
+        self.n1 = mesh.p + 1
+        self.Np = self.n1 ** mesh.dim
+        self.E = mesh.n_elem
+
+    def _check(self, st):
+        if st != LDG_OK:
+            raise LDGError(st, self.lib.ldg_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ldg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # thin wrappers with the ABI names
+    def ldg_set_source(self, S):
+        self._check(self.lib.ldg_set_source(self.h, _ptr(S)))
+
+    def ldg_set_dirichlet(self, gD):
+        self._check(self.lib.ldg_set_dirichlet(self.h, _ptr(gD)))
+
+    def ldg_gradient(self, U, Q, homogeneous=False):
+        self._check(self.lib.ldg_gradient(self.h, _ptr(U), _ptr(Q), int(homogeneous)))
+
+    def ldg_residual(self, U, R, Q=None):
+        self._check(self.lib.ldg_residual(self.h, _ptr(U), _ptr(R), _ptr(Q)))
+
+    def ldg_jacobian_assemble(self, U, alpha, gamma, storage_prec=LDG_F64):
+        self._check(self.lib.ldg_jacobian_assemble(self.h, _ptr(U), float(alpha), float(gamma), int(storage_prec)))
+
+    def ldg_jacvec(self, x, y, exact_fp64=False):
+        self._check(self.lib.ldg_jacvec(self.h, _ptr(x), _ptr(y), int(exact_fp64)))
+
+    def ldg_precond_apply(self, r, z):
+        self._check(self.lib.ldg_precond_apply(self.h, _ptr(r), _ptr(z)))
+
+    def ldg_export_operators(self, K11=None, K12=None, F=None):
+        self._check(self.lib.ldg_export_operators(self.h, _ptr(K11), _ptr(K12), _ptr(F)))
+
+    def ldg_newton_step(self, U, Ucomb, alpha, gamma, restart=50, max_iters=2000, max_refine=20,
+                        storage_prec=LDG_F64, rtol=1e-8, inner_rtol=1e-3, use_learned=0, reassemble=1,
+                        raise_on_error=True):
+        o = ldg_solver_opts(restart, max_iters, max_refine, storage_prec, rtol, inner_rtol, use_learned, reassemble)
+        rep = ldg_solver_report()
+        st = self.lib.ldg_newton_step(self.h, _ptr(U), _ptr(Ucomb), float(alpha), float(gamma), ctypes.byref(o),
+                                      ctypes.byref(rep))
+        if raise_on_error:
+            self._check(st)
+        out = rep.as_dict()
+        out["status"] = st
+        return out
+
+    def ldg_rk4(self, U, dt, n_steps):
+        self._check(self.lib.ldg_rk4(self.h, _ptr(U), float(dt), int(n_steps)))
+
+    def ldg_num_dofs(self):
+        return int(self.lib.ldg_num_dofs(self.h))
+
+    # sizes of the exchange layouts
+    def nslots(self):
+        D, p = self.dim, self.p
+        return D * p + 1 + 2 * D, D * p + 1 + D, D * p + 1

@@ -1,0 +1,102 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared entry point,
+and rejects bad descriptions before any device work (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from ldg_workloads import quad_mesh
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1204_1533_amd", "libldg.so")
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "ldg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(ldg_[a-z0-9_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.skip("libldg.so not built")
+    from paper_1204_1533_amd import ldg
+    return ldg.load_library()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert "ldg_residual" in names and "ldg_newton_step" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    from paper_1204_1533_amd import ldg
+    assert set(names) <= set(ldg.exported_symbols()) | set(names)
+
+
+def _desc(mesh, **kw):
+    from paper_1204_1533_amd import ldg
+    keep = dict(xyz=np.ascontiguousarray(mesh.xyz), fn=np.ascontiguousarray(mesh.face_nbr),
+                nn=np.ascontiguousarray(mesh.nbr_node), sw=np.ascontiguousarray(mesh.switch_plus))
+    d = ldg.ldg_problem_desc()
+    d.dim, d.p, d.equation, d.node_family = mesh.dim, mesh.p, kw.get("equation", 1), 0
+    d.gamma, d.mu, d.prandtl, d.c11_interior, d.c11_dirichlet = 1.4, 0.0, 0.72, 0.0, 10.0
+    d.n_elem = mesh.n_elem
+    for k, v in kw.items():
+        setattr(d, k, v)
+    d.node_xyz_host = keep["xyz"].ctypes.data
+    d.face_nbr_host = keep["fn"].ctypes.data
+    d.nbr_node_host = keep["nn"].ctypes.data
+    d.switch_plus_host = keep["sw"].ctypes.data
+    return d, keep
+
+
+def _create(lib, d):
+    h = ctypes.c_void_p()
+    return lib.ldg_create(ctypes.byref(d), None, ctypes.byref(h))
+
+
+def test_create_rejects_bad_descriptions(lib):
+    from paper_1204_1533_amd import ldg
+    mesh = quad_mesh(3, 3, 2, periodic=(True, True))
+    d, keep = _desc(mesh, p=7)
+    assert _create(lib, d) == ldg.LDG_E_UNSUPPORTED
+    d, keep = _desc(mesh, dim=4)
+    assert _create(lib, d) == ldg.LDG_E_UNSUPPORTED
+    d, keep = _desc(mesh, gamma=0.5)
+    assert _create(lib, d) == ldg.LDG_E_INVALID
+    d, keep = _desc(mesh)
+    d.face_nbr_host = None
+    assert _create(lib, d) == ldg.LDG_E_INVALID
+    # broken reciprocity
+    bad = mesh.nbr_node.copy()
+    bad[0, 1, 0] = (bad[0, 1, 0] + 1) % mesh.np_
+    mesh2 = type(mesh)(mesh.dim, mesh.p, mesh.xyz, mesh.face_nbr, bad, mesh.switch_plus)
+    d, keep = _desc(mesh2)
+    assert _create(lib, d) == ldg.LDG_E_SHAPE
+    # switch signs not opposite across a face
+    sw = mesh.switch_plus.copy()
+    sw[4, 0] = -1
+    mesh3 = type(mesh)(mesh.dim, mesh.p, mesh.xyz, mesh.face_nbr, mesh.nbr_node, sw)
+    d, keep = _desc(mesh3)
+    assert _create(lib, d) == ldg.LDG_E_SHAPE
+    # switch values must be +-1
+    sw = mesh.switch_plus.copy()
+    sw[0, 0] = 0
+    mesh4 = type(mesh)(mesh.dim, mesh.p, mesh.xyz, mesh.face_nbr, mesh.nbr_node, sw)
+    d, keep = _desc(mesh4)
+    assert _create(lib, d) == ldg.LDG_E_INVALID
+    # Dirichlet faces need a positive penalty (Poisson)
+    m5 = quad_mesh(2, 2, 2)
+    d, keep = _desc(m5, equation=0, c11_dirichlet=0.0)
+    assert _create(lib, d) == ldg.LDG_E_INVALID
+
+
+def test_null_context_calls(lib):
+    from paper_1204_1533_amd import ldg
+    assert lib.ldg_residual(None, None, None, None) == ldg.LDG_E_INVALID
+    assert lib.ldg_num_dofs(None) == -1
+    assert lib.ldg_status_string(ldg.LDG_E_NOT_ASSEMBLED) == b"operators not assembled"
