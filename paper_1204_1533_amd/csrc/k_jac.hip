@@ -232,12 +232,12 @@ __global__ void __launch_bounds__(NT_ELEM) jac_kernel(LineOps ops, MeshParams mp
                 if (side == 0) tqi[c * D + dq].d[c] = 1.0;
                 else tqo[c * D + dq].d[c] = 1.0;
               }
-              face_flux_point<D, EQ, T, false>(ti, tqi, to, tqo, nrm, S, bnd, mp, F);
+              face_flux_point_io<D, EQ, T, false>(ti, tqi, to, tqo, nrm, S, bnd, mp, F);
             } else {
-              face_flux_point<D, EQ, T, true>(ti, tqi, to, tqo, nrm, S, bnd, mp, F);
+              face_flux_point_io<D, EQ, T, true>(ti, tqi, to, tqo, nrm, S, bnd, mp, F);
             }
           } else {
-            face_flux_point<D, EQ, T, true>(ti, ti, to, to, nrm, S, bnd, mp, F);
+            face_flux_point_io<D, EQ, T, true>(ti, ti, to, to, nrm, S, bnd, mp, F);
           }
 #pragma unroll
           for (int c = 0; c < M; ++c)

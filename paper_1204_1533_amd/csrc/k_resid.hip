@@ -81,6 +81,9 @@ __device__ __forceinline__ void node_G(const double* sG, int node, int NP, doubl
 }
 
 // --------------------------------------------------------------------------- residual
+// Same organisation as the gradient kernel below: directions one after
+// another, each thread owns fixed (element, component, node) outputs and
+// accumulates the D line contributions in registers.
 template <int D, int P, int EQ, class T>
 struct ResidLayout {
   static constexpr int N1 = P + 1, NG = n_gauss(P), NP = ipow(N1, D), NL = ipow(N1, D - 1);
@@ -88,14 +91,19 @@ struct ResidLayout {
   static constexpr bool VIS = Eq<D, EQ>::VIS;
   static constexpr int EPB = elems_per_block(NP, M);
   static constexpr int QW = VIS ? M * D : 0;
-  // byte offsets (T first, then doubles; all multiples of 16)
+  // byte offsets (T arrays first, then doubles; all multiples of 16)
   static constexpr size_t oU = 0;
   static constexpr size_t oQ = oU + sizeof(T) * EPB * M * NP;
+  static constexpr int NW = M + QW;  // state and gradient components interpolated to a Gauss point
   static constexpr size_t oF = oQ + sizeof(T) * EPB * QW * NP;
-  static constexpr size_t oH = oF + sizeof(T) * EPB * D * NL * NG * M;
-  static constexpr size_t oX = oH + sizeof(T) * EPB * D * NL * 2 * M;
+  static constexpr size_t oH = oF + sizeof(T) * EPB * NL * NG * M;
+  static constexpr size_t oW = oH + sizeof(T) * EPB * NL * 2 * M;
+  static constexpr size_t oX = oW + sizeof(T) * EPB * NL * NG * NW;
   static constexpr size_t oG = oX + sizeof(double) * EPB * D * NP;
-  static constexpr size_t bytes = oG + sizeof(double) * EPB * D * D * NP;
+  static constexpr size_t oJ = oG + sizeof(double) * EPB * D * D * NP;
+  static constexpr size_t oA = oJ + sizeof(double) * EPB * NP;
+  static constexpr size_t bytes = oA + sizeof(double) * EPB * NL * NG * D;
+  static constexpr int NITEM = (EPB * M * NP + NT_ELEM - 1) / NT_ELEM;
 };
 
 template <int D, int P, int EQ, class T>
@@ -112,6 +120,10 @@ __global__ void __launch_bounds__(NT_ELEM) resid_kernel(LineOps ops, MeshParams 
   T* sH = reinterpret_cast<T*>(smem_raw + L::oH);
   double* sX = reinterpret_cast<double*>(smem_raw + L::oX);
   double* sG = reinterpret_cast<double*>(smem_raw + L::oG);
+  double* sJ = reinterpret_cast<double*>(smem_raw + L::oJ);
+  T* sWg = reinterpret_cast<T*>(smem_raw + L::oW);
+  double* sAg = reinterpret_cast<double*>(smem_raw + L::oA);
+  constexpr int NW = L::NW;
 
   const int64_t e0 = (int64_t)blockIdx.x * EPB;
   const int ne = (int)min((int64_t)EPB, mp.E - e0);
@@ -128,130 +140,158 @@ __global__ void __launch_bounds__(NT_ELEM) resid_kernel(LineOps ops, MeshParams 
     nodal_G_item<D, N1>(sX + e * D * NP, sG + e * D * D * NP, ops, node, ab / D, ab % D, NP);
   }
   __syncthreads();
-
-  // Gauss phase: contravariant flux at every line Gauss point
-  for (int i = tid; i < ne * D * NL * NG; i += NT_ELEM) {
-    const int e = i / (D * NL * NG), r = i % (D * NL * NG);
-    const int n = r / (NL * NG), l = (r / NG) % NL, g = r % NG;
-    double an[D];
-    gauss_metric<D, N1>(sX + e * D * NP, sG + e * D * D * NP, ops, n, l, g, NP, an);
-    T ug[M];
-#pragma unroll
-    for (int c = 0; c < M; ++c) {
-      T acc = cst<T>(0.0);
-#pragma unroll
-      for (int t = 0; t < N1; ++t) acc += ops.I[g][t] * sU[(e * M + c) * NP + line_node<D, N1>(n, l, t)];
-      ug[c] = acc;
-    }
-    T f[M];
-#pragma unroll
-    for (int c = 0; c < M; ++c) f[c] = cst<T>(0.0);
-    if constexpr (INV) euler_flux_dot<D, T>(ug, an, mp.gamma, f);
-    if constexpr (VIS) {
-      T qg[M * D];
-#pragma unroll
-      for (int c = 0; c < M * D; ++c) {
-        T acc = cst<T>(0.0);
-#pragma unroll
-        for (int t = 0; t < N1; ++t) acc += ops.I[g][t] * sQ[(e * QW + c) * NP + line_node<D, N1>(n, l, t)];
-        qg[c] = acc;
-      }
-      visc_flux_dot_add<D, EQ, T>(ug, qg, an, mp.gamma, mp.mu, mp.prandtl, f);
-    }
-#pragma unroll
-    for (int c = 0; c < M; ++c) sF[(((e * D + n) * NL + l) * NG + g) * M + c] = f[c];
+  for (int i = tid; i < ne * NP; i += NT_ELEM) {
+    double G[D][D];
+    node_G<D>(sG + (i / NP) * D * D * NP, i % NP, NP, G);
+    sJ[i] = -1.0 / det<D>(G);
   }
+  T acc[L::NITEM];
+#pragma unroll
+  for (int q = 0; q < L::NITEM; ++q) acc[q] = cst<T>(0.0);
 
-  // face phase: point fluxes at both ends of every line
-  for (int i = tid; i < ne * D * NL * 2; i += NT_ELEM) {
-    const int e = i / (D * NL * 2), r = i % (D * NL * 2);
-    const int n = r / (NL * 2), l = (r / 2) % NL, s = r % 2;
-    const int64_t eg = e0 + e;
-    const int nin = line_node<D, N1>(n, l, s ? P : 0);
-    double G[D][D], an[D], nrm[D];
-    node_G<D>(sG + e * D * D * NP, nin, NP, G);
-    cofactor_row<D>(G, n, an);
 #pragma unroll
-    for (int d = 0; d < D; ++d) nrm[d] = s ? an[d] : -an[d];
-    const int f = 2 * n + s;
-    const int64_t nb = mp.face_nbr[eg * 2 * D + f];
-    const bool bnd = nb < 0;
-    T uin[M], uout[M];
+  for (int n = 0; n < D; ++n) {
+    // interpolation phase: state, gradient and non-unit normal a_n at every Gauss point
+    for (int i = tid; i < ne * NL * NG * NW; i += NT_ELEM) {
+      const int k = i % NW, pt = i / NW;
+      const int e = pt / (NL * NG), l = (pt / NG) % NL, g = pt % NG;
+      const T* src = k < M ? sU + (e * M + k) * NP : sQ + (e * QW + (k - M)) * NP;
+      T a = cst<T>(0.0);
 #pragma unroll
-    for (int c = 0; c < M; ++c) uin[c] = sU[(e * M + c) * NP + nin];
-    int nd = 0;
-    if (!bnd) {
-      nd = mp.nbr_node[(eg * 2 * D + f) * NL + l];
-#pragma unroll
-      for (int c = 0; c < M; ++c) uout[c] = IO<T>::load(U, Ut, (nb * M + c) * NP + nd);
-    } else {
-#pragma unroll
-      for (int c = 0; c < M; ++c) uout[c] = cst<T>(mp.gD ? mp.gD[((eg * 2 * D + f) * M + c) * NL + l] : 0.0);
+      for (int t = 0; t < N1; ++t) a += ops.I[g][t] * src[line_node<D, N1>(n, l, t)];
+      sWg[i] = a;
     }
-    T F[M];
-    if constexpr (VIS) {
-      T qin[M * D], qout[M * D];
+    for (int i = tid; i < ne * NL * NG; i += NT_ELEM) {
+      const int e = i / (NL * NG), l = (i / NG) % NL, g = i % NG;
+      double an[D];
+      gauss_metric<D, N1>(sX + e * D * NP, sG + e * D * D * NP, ops, n, l, g, NP, an);
 #pragma unroll
-      for (int c = 0; c < M * D; ++c) qin[c] = sQ[(e * QW + c) * NP + nin];
-      const int Sp = mp.sw[eg * D + n];
-      const int S = s ? Sp : -Sp;
-      if (!bnd && S > 0) {
+      for (int d = 0; d < D; ++d) sAg[i * D + d] = an[d];
+    }
+    __syncthreads();
+    // Gauss phase: contravariant flux F . a_n at every Gauss point of the direction-n lines
+    for (int i = tid; i < ne * NL * NG; i += NT_ELEM) {
+      double an[D];
 #pragma unroll
-        for (int c = 0; c < M * D; ++c) qout[c] = IO<T>::load(Q, Qt, (nb * QW + c) * NP + nd);
+      for (int d = 0; d < D; ++d) an[d] = sAg[i * D + d];
+      const T* w = sWg + i * NW;
+      T ug[M];
+#pragma unroll
+      for (int c = 0; c < M; ++c) ug[c] = w[c];
+      T f[M];
+#pragma unroll
+      for (int c = 0; c < M; ++c) f[c] = cst<T>(0.0);
+      if constexpr (INV) euler_flux_dot<D, T>(ug, an, mp.gamma, f);
+      if constexpr (VIS) {
+        T qg[M * D];
+#pragma unroll
+        for (int c = 0; c < M * D; ++c) qg[c] = w[M + c];
+        visc_flux_dot_add<D, EQ, T>(ug, qg, an, mp.gamma, mp.mu, mp.prandtl, f);
+      }
+#pragma unroll
+      for (int c = 0; c < M; ++c) sF[i * M + c] = f[c];
+    }
+    // face phase: point fluxes at both ends of every direction-n line
+    for (int i = tid; i < ne * NL * 2; i += NT_ELEM) {
+      const int e = i / (NL * 2), l = (i / 2) % NL, s = i % 2;
+      const int64_t eg = e0 + e;
+      const int nin = line_node<D, N1>(n, l, s ? P : 0);
+      double G[D][D], an[D], nrm[D];
+      node_G<D>(sG + e * D * D * NP, nin, NP, G);
+      cofactor_row<D>(G, n, an);
+#pragma unroll
+      for (int d = 0; d < D; ++d) nrm[d] = s ? an[d] : -an[d];
+      const int f = 2 * n + s;
+      const int64_t nb = mp.face_nbr[eg * 2 * D + f];
+      const bool bnd = nb < 0;
+      T uin[M], uout[M];
+#pragma unroll
+      for (int c = 0; c < M; ++c) uin[c] = sU[(e * M + c) * NP + nin];
+      int nd = 0;
+      if (!bnd) {
+        nd = mp.nbr_node[(eg * 2 * D + f) * NL + l];
+#pragma unroll
+        for (int c = 0; c < M; ++c) uout[c] = IO<T>::load(U, Ut, (nb * M + c) * NP + nd);
       } else {
 #pragma unroll
-        for (int c = 0; c < M * D; ++c) qout[c] = qin[c];
+        for (int c = 0; c < M; ++c) uout[c] = cst<T>(mp.gD ? mp.gD[((eg * 2 * D + f) * M + c) * NL + l] : 0.0);
       }
-      face_flux_point<D, EQ, T>(uin, qin, uout, qout, nrm, S, bnd, mp, F);
-    } else {
-      face_flux_point<D, EQ, T>(uin, uin, uout, uout, nrm, 1, bnd, mp, F);
-    }
+      T F[M];
+      if constexpr (VIS) {
+        const int Sp = mp.sw[eg * D + n];
+        const int S = s ? Sp : -Sp;
+        T qsel[M * D];
+        if (!bnd && S > 0) {
 #pragma unroll
-    for (int c = 0; c < M; ++c) sH[(((e * D + n) * NL + l) * 2 + s) * M + c] = F[c];
+          for (int c = 0; c < M * D; ++c) qsel[c] = IO<T>::load(Q, Qt, (nb * QW + c) * NP + nd);
+        } else {
+#pragma unroll
+          for (int c = 0; c < M * D; ++c) qsel[c] = sQ[(e * QW + c) * NP + nin];
+        }
+        face_flux_point<D, EQ, T>(uin, uout, qsel, nrm, S, bnd, mp, F);
+      } else {
+        face_flux_point<D, EQ, T>(uin, uout, uin, nrm, 1, bnd, mp, F);
+      }
+#pragma unroll
+      for (int c = 0; c < M; ++c) sH[i * M + c] = F[c];
+    }
+    __syncthreads();
+    // projection of this direction's line problems onto the owned outputs
+#pragma unroll
+    for (int q = 0; q < L::NITEM; ++q) {
+      const int i = tid + q * NT_ELEM;
+      if (i < ne * M * NP) {
+        const int e = i / (M * NP), r = i % (M * NP);
+        const int c = r / NP, node = r % NP;
+        int l, t;
+        node_line<N1>(node, n, l, t);
+        const T* h = sH + (e * NL + l) * 2 * M;
+        T a = ops.L1[t] * h[M + c] + ops.L0[t] * h[c];
+        const T* fl = sF + (e * NL + l) * NG * M;
+#pragma unroll
+        for (int g = 0; g < NG; ++g) a -= ops.V[t][g] * fl[g * M + c];
+        acc[q] += a;
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
-
-  // projection, sum over directions, -1/J scaling
-  for (int i = tid; i < ne * M * NP; i += NT_ELEM) {
-    const int e = i / (M * NP), r = i % (M * NP);
-    const int c = r / NP, node = r % NP;
-    T acc = cst<T>(0.0);
 #pragma unroll
-    for (int n = 0; n < D; ++n) {
-      int l, t;
-      node_line<N1>(node, n, l, t);
-      const T* h = sH + ((e * D + n) * NL + l) * 2 * M;
-      acc += ops.L1[t] * h[M + c] + ops.L0[t] * h[c];
-      const T* fl = sF + ((e * D + n) * NL + l) * NG * M;
-#pragma unroll
-      for (int g = 0; g < NG; ++g) acc -= ops.V[t][g] * fl[g * M + c];
+  for (int q = 0; q < L::NITEM; ++q) {
+    const int i = tid + q * NT_ELEM;
+    if (i < ne * M * NP) {
+      const int e = i / (M * NP), node = i % NP;
+      const int64_t gi = e0 * M * NP + i;
+      double out = tangent_or_value(acc[q]) * sJ[e * NP + node];
+      if constexpr (sizeof(T) == sizeof(double)) {
+        if (mp.S) out += mp.S[gi];
+      }
+      R[gi] = out;
     }
-    double G[D][D];
-    node_G<D>(sG + e * D * D * NP, node, NP, G);
-    const double J = det<D>(G);
-    const int64_t gi = e0 * M * NP + i;
-    double out = -tangent_or_value(acc) / J;
-    if constexpr (sizeof(T) == sizeof(double)) {
-      if (mp.S) out += mp.S[gi];
-    }
-    R[gi] = out;
   }
 }
 
 // --------------------------------------------------------------------------- gradient
+// Directions are processed one after another with compile-time indexing; each
+// thread owns fixed output entries (element, component, derivative, node) and
+// accumulates the D line contributions in registers, so only one direction's
+// Gauss-point and face data live in LDS at a time.
 template <int D, int P, int EQ>
 struct GradLayout {
   static constexpr int N1 = P + 1, NG = n_gauss(P), NP = ipow(N1, D), NL = ipow(N1, D - 1);
   static constexpr int M = Eq<D, EQ>::M;
   static constexpr int EPB = elems_per_block(NP, M);
-  static constexpr size_t oU = 0;
-  static constexpr size_t oUg = oU + 8 * EPB * M * NP;
-  static constexpr size_t oAg = oUg + 8 * EPB * D * NL * NG * M;
-  static constexpr size_t oUh = oAg + 8 * EPB * D * NL * NG * D;
-  static constexpr size_t oNh = oUh + 8 * EPB * D * NL * 2 * M;
-  static constexpr size_t oX = oNh + 8 * EPB * D * NL * 2 * D;
-  static constexpr size_t oG = oX + 8 * EPB * D * NP;
-  static constexpr size_t bytes = oG + 8 * EPB * D * D * NP;
+  static constexpr int oU = 0;
+  static constexpr int oX = oU + EPB * M * NP;
+  static constexpr int oG = oX + EPB * D * NP;
+  static constexpr int oJ = oG + EPB * D * D * NP;
+  static constexpr int oUg = oJ + EPB * NP;
+  static constexpr int oAg = oUg + EPB * NL * NG * M;
+  static constexpr int oUh = oAg + EPB * NL * NG * D;
+  static constexpr int oNh = oUh + EPB * NL * 2 * M;
+  static constexpr int ndoubles = oNh + EPB * NL * 2 * D;
+  static constexpr size_t bytes = 8 * (size_t)ndoubles;
+  static constexpr int NOUT = EPB * M * D * NP;
+  static constexpr int NITEM = (NOUT + NT_ELEM - 1) / NT_ELEM;
 };
 
 template <int D, int P, int EQ>
@@ -260,13 +300,15 @@ __global__ void __launch_bounds__(NT_ELEM) grad_kernel(LineOps ops, MeshParams m
   using L = GradLayout<D, P, EQ>;
   constexpr int N1 = L::N1, NG = L::NG, NP = L::NP, NL = L::NL, M = L::M, EPB = L::EPB;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* sU = reinterpret_cast<double*>(smem_raw + L::oU);
-  double* sUg = reinterpret_cast<double*>(smem_raw + L::oUg);
-  double* sAg = reinterpret_cast<double*>(smem_raw + L::oAg);
-  double* sUh = reinterpret_cast<double*>(smem_raw + L::oUh);
-  double* sNh = reinterpret_cast<double*>(smem_raw + L::oNh);
-  double* sX = reinterpret_cast<double*>(smem_raw + L::oX);
-  double* sG = reinterpret_cast<double*>(smem_raw + L::oG);
+  double* sm = reinterpret_cast<double*>(smem_raw);
+  double* sU = sm + L::oU;
+  double* sX = sm + L::oX;
+  double* sG = sm + L::oG;
+  double* sJ = sm + L::oJ;
+  double* sUg = sm + L::oUg;
+  double* sAg = sm + L::oAg;
+  double* sUh = sm + L::oUh;
+  double* sNh = sm + L::oNh;
 
   const int64_t e0 = (int64_t)blockIdx.x * EPB;
   const int ne = (int)min((int64_t)EPB, mp.E - e0);
@@ -280,68 +322,83 @@ __global__ void __launch_bounds__(NT_ELEM) grad_kernel(LineOps ops, MeshParams m
     nodal_G_item<D, N1>(sX + e * D * NP, sG + e * D * D * NP, ops, node, ab / D, ab % D, NP);
   }
   __syncthreads();
-  for (int i = tid; i < ne * D * NL * NG; i += NT_ELEM) {
-    const int e = i / (D * NL * NG), r = i % (D * NL * NG);
-    const int n = r / (NL * NG), l = (r / NG) % NL, g = r % NG;
-    double an[D];
-    gauss_metric<D, N1>(sX + e * D * NP, sG + e * D * D * NP, ops, n, l, g, NP, an);
-    const int o = ((e * D + n) * NL + l) * NG + g;
-#pragma unroll
-    for (int d = 0; d < D; ++d) sAg[o * D + d] = an[d];
-#pragma unroll
-    for (int c = 0; c < M; ++c) {
-      double acc = 0.0;
-#pragma unroll
-      for (int t = 0; t < N1; ++t) acc += ops.I[g][t] * sU[(e * M + c) * NP + line_node<D, N1>(n, l, t)];
-      sUg[o * M + c] = acc;
-    }
-  }
-  for (int i = tid; i < ne * D * NL * 2; i += NT_ELEM) {
-    const int e = i / (D * NL * 2), r = i % (D * NL * 2);
-    const int n = r / (NL * 2), l = (r / 2) % NL, s = r % 2;
-    const int64_t eg = e0 + e;
-    const int nin = line_node<D, N1>(n, l, s ? P : 0);
-    double G[D][D], an[D];
-    node_G<D>(sG + e * D * D * NP, nin, NP, G);
-    cofactor_row<D>(G, n, an);
-    const int o = ((e * D + n) * NL + l) * 2 + s;
-#pragma unroll
-    for (int d = 0; d < D; ++d) sNh[o * D + d] = s ? an[d] : -an[d];
-    const int f = 2 * n + s;
-    const int64_t nb = mp.face_nbr[eg * 2 * D + f];
-    const int Sp = mp.sw[eg * D + n];
-    const int S = s ? Sp : -Sp;
-    if (nb < 0) {
-#pragma unroll
-      for (int c = 0; c < M; ++c)
-        sUh[o * M + c] = (homogeneous || !mp.gD) ? 0.0 : mp.gD[((eg * 2 * D + f) * M + c) * NL + l];
-    } else if (S > 0) {
-#pragma unroll
-      for (int c = 0; c < M; ++c) sUh[o * M + c] = sU[(e * M + c) * NP + nin];
-    } else {
-      const int nd = mp.nbr_node[(eg * 2 * D + f) * NL + l];
-#pragma unroll
-      for (int c = 0; c < M; ++c) sUh[o * M + c] = U[(nb * M + c) * NP + nd];
-    }
-  }
-  __syncthreads();
-  for (int i = tid; i < ne * M * D * NP; i += NT_ELEM) {
-    const int e = i / (M * D * NP), r = i % (M * D * NP);
-    const int c = r / (D * NP), d = (r / NP) % D, node = r % NP;
-    double acc = 0.0;
-#pragma unroll
-    for (int n = 0; n < D; ++n) {
-      int l, t;
-      node_line<N1>(node, n, l, t);
-      const int oh = ((e * D + n) * NL + l) * 2;
-      acc += ops.L1[t] * sUh[(oh + 1) * M + c] * sNh[(oh + 1) * D + d] + ops.L0[t] * sUh[oh * M + c] * sNh[oh * D + d];
-      const int og = ((e * D + n) * NL + l) * NG;
-#pragma unroll
-      for (int g = 0; g < NG; ++g) acc -= ops.V[t][g] * sUg[(og + g) * M + c] * sAg[(og + g) * D + d];
-    }
+  for (int i = tid; i < ne * NP; i += NT_ELEM) {
     double G[D][D];
-    node_G<D>(sG + e * D * D * NP, node, NP, G);
-    Q[e0 * M * D * NP + i] = acc / det<D>(G);
+    node_G<D>(sG + (i / NP) * D * D * NP, i % NP, NP, G);
+    sJ[i] = 1.0 / det<D>(G);
+  }
+  double acc[L::NITEM];
+#pragma unroll
+  for (int q = 0; q < L::NITEM; ++q) acc[q] = 0.0;
+#pragma unroll
+  for (int n = 0; n < D; ++n) {
+    for (int i = tid; i < ne * NL * NG; i += NT_ELEM) {
+      const int e = i / (NL * NG), l = (i / NG) % NL, g = i % NG;
+      double an[D];
+      gauss_metric<D, N1>(sX + e * D * NP, sG + e * D * D * NP, ops, n, l, g, NP, an);
+#pragma unroll
+      for (int d = 0; d < D; ++d) sAg[i * D + d] = an[d];
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        double a = 0.0;
+#pragma unroll
+        for (int t = 0; t < N1; ++t) a += ops.I[g][t] * sU[(e * M + c) * NP + line_node<D, N1>(n, l, t)];
+        sUg[i * M + c] = a;
+      }
+    }
+    for (int i = tid; i < ne * NL * 2; i += NT_ELEM) {
+      const int e = i / (NL * 2), l = (i / 2) % NL, s = i % 2;
+      const int64_t eg = e0 + e;
+      const int nin = line_node<D, N1>(n, l, s ? P : 0);
+      double G[D][D], an[D];
+      node_G<D>(sG + e * D * D * NP, nin, NP, G);
+      cofactor_row<D>(G, n, an);
+#pragma unroll
+      for (int d = 0; d < D; ++d) sNh[i * D + d] = s ? an[d] : -an[d];
+      const int f = 2 * n + s;
+      const int64_t nb = mp.face_nbr[eg * 2 * D + f];
+      const int Sp = mp.sw[eg * D + n];
+      const int S = s ? Sp : -Sp;
+      if (nb < 0) {
+#pragma unroll
+        for (int c = 0; c < M; ++c)
+          sUh[i * M + c] = (homogeneous || !mp.gD) ? 0.0 : mp.gD[((eg * 2 * D + f) * M + c) * NL + l];
+      } else if (S > 0) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) sUh[i * M + c] = sU[(e * M + c) * NP + nin];
+      } else {
+        const int nd = mp.nbr_node[(eg * 2 * D + f) * NL + l];
+#pragma unroll
+        for (int c = 0; c < M; ++c) sUh[i * M + c] = U[(nb * M + c) * NP + nd];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < L::NITEM; ++q) {
+      const int i = tid + q * NT_ELEM;
+      if (i < ne * M * D * NP) {
+        const int e = i / (M * D * NP), r = i % (M * D * NP);
+        const int c = r / (D * NP), d = (r / NP) % D, node = r % NP;
+        int l, t;
+        node_line<N1>(node, n, l, t);
+        const int oh = (e * NL + l) * 2;
+        double a = ops.L1[t] * sUh[(oh + 1) * M + c] * sNh[(oh + 1) * D + d] +
+                   ops.L0[t] * sUh[oh * M + c] * sNh[oh * D + d];
+        const int og = (e * NL + l) * NG;
+#pragma unroll
+        for (int g = 0; g < NG; ++g) a -= ops.V[t][g] * sUg[(og + g) * M + c] * sAg[(og + g) * D + d];
+        acc[q] += a;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < L::NITEM; ++q) {
+    const int i = tid + q * NT_ELEM;
+    if (i < ne * M * D * NP) {
+      const int e = i / (M * D * NP), node = i % NP;
+      Q[e0 * M * D * NP + i] = acc[q] * sJ[e * NP + node];
+    }
   }
 }
 

@@ -197,13 +197,15 @@ __device__ __forceinline__ void euler_flux_dot(const T* u, const double* a, doub
 }
 
 // f[c] += F^vis(u, q)[c][:] . a  (NS: F^vis = -(0, tau_ij, u_i tau_ij - q_j); q_j = -(mu/Pr) dh/dx_j)
-template <int D, int EQ, class T>
-__device__ __forceinline__ void visc_flux_dot_add(const T* u, const T* q /*[M][D]*/, const double* a,
+// The gradient may have a different scalar type TQ than the state (e.g. plain
+// doubles while the state carries tangents); F^vis is linear in q.
+template <int D, int EQ, class T, class TQ = T>
+__device__ __forceinline__ void visc_flux_dot_add(const T* u, const TQ* q /*[M][D]*/, const double* a,
                                                   double gamma, double mu, double prandtl, T* f) {
   if constexpr (EQ == EQ_POISSON) {
     T s = cst<T>(0.0);
 #pragma unroll
-    for (int d = 0; d < D; ++d) s += q[d] * a[d];
+    for (int d = 0; d < D; ++d) s = s + q[d] * a[d];
     f[0] -= s;
   } else {
     const T irho = 1.0 / u[0];
@@ -216,7 +218,7 @@ __device__ __forceinline__ void visc_flux_dot_add(const T* u, const T* q /*[M][D
     T div = cst<T>(0.0);
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-      const T dr = q[0 * D + j];
+      const TQ dr = q[0 * D + j];
       T dE = (q[(D + 1) * D + j] - Esp * dr) * irho;
       T kin = cst<T>(0.0);
 #pragma unroll
@@ -363,10 +365,39 @@ namespace ldg {
 //             inside state when S = -1, dotted with n, plus C11 |n| (u_in - u_out);
 //             on a Dirichlet face F^vis(u_in, q_in) . n + C11_D |n| (u_in - g_D)
 //             (u_out holds g_D there).
-// qout is read only for an interior face with S = +1.
+// qsel is the gradient of the side whose viscous flux is taken: the outside
+// for an interior face with S = +1, the inside otherwise.  The viscous part is
+// evaluated first so the gradient is dead before the Riemann solve.
+template <int D, int EQ, class T, bool WITH_INV = true, class TQ = T>
+__device__ __forceinline__ void face_flux_point(const T* uin, const T* uout, const TQ* qsel, const double* nrm,
+                                                int S, bool bnd, const MeshParams& mp, T* F) {
+  constexpr int M = Eq<D, EQ>::M;
+#pragma unroll
+  for (int c = 0; c < M; ++c) F[c] = cst<T>(0.0);
+  if constexpr (Eq<D, EQ>::VIS) {
+    double nn = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) nn += nrm[d] * nrm[d];
+    nn = sqrt(nn);
+    const bool use_out = !bnd && S > 0;
+    visc_flux_dot_add<D, EQ, T, TQ>(use_out ? uout : uin, qsel, nrm, mp.gamma, mp.mu, mp.prandtl, F);
+    const double c11 = bnd ? mp.c11d : mp.c11i;
+#pragma unroll
+    for (int c = 0; c < M; ++c) F[c] += (c11 * nn) * (uin[c] - uout[c]);
+  }
+  if constexpr (Eq<D, EQ>::INV && WITH_INV) {
+    T Fr[M];
+    roe_flux<D, T>(uout, uin, nrm, mp.gamma, Fr);
+#pragma unroll
+    for (int c = 0; c < M; ++c) F[c] += Fr[c];
+  }
+}
+
+// Same point flux with both sides' gradients given (the assembly kernel's
+// form): qin is the inside gradient, qout the outside one.
 template <int D, int EQ, class T, bool WITH_INV = true>
-__device__ __forceinline__ void face_flux_point(const T* uin, const T* qin, const T* uout, const T* qout,
-                                                const double* nrm, int S, bool bnd, const MeshParams& mp, T* F) {
+__device__ __forceinline__ void face_flux_point_io(const T* uin, const T* qin, const T* uout, const T* qout,
+                                                   const double* nrm, int S, bool bnd, const MeshParams& mp, T* F) {
   constexpr int M = Eq<D, EQ>::M;
 #pragma unroll
   for (int c = 0; c < M; ++c) F[c] = cst<T>(0.0);
