@@ -34,7 +34,73 @@ def parse():
     ap.add_argument("--config", default="C4", choices=["C3", "C4"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=256, help="elements timed on the CPU oracle")
     return ap.parse_args()
+
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def roofline(pr, reps, prec):
+    """Achieved bandwidth of the solver's stream-timed kernels (HIP events inside the step).
+
+    Algorithmic bytes per node (m components, D dimensions, p degree, e bytes per stored entry):
+      split product: K11 (Dp+1+2D) m^2 e + K12 (Dp+1+D) m^2 D e + x 8m + w = K21 x 8mD + y 8m
+      ILU(0) apply : factors (Dp+1) m^2 e + r 8m + z 8m
+      K21 x        : x 8m + node coordinates 8D + w 8mD
+    """
+    import numpy as np
+    me = pr.mesh
+    D, p, m = me.dim, me.p, pr.m
+    e = {0: 8, 1: 4, 2: 2}[prec]
+    nodes = me.n_elem * me.np_
+    per_node = {
+        "jacvec": (D * p + 1 + 2 * D) * m * m * e + (D * p + 1 + D) * m * m * D * e + 8 * m + 8 * m * D + 8 * m,
+        "precond_apply": (D * p + 1) * m * m * e + 16 * m,
+        "k21_gradient": 8 * m + 8 * D + 8 * m * D,
+    }
+    keys = {"jacvec": ("t_jacvec_ms", "n_jacvec"), "precond_apply": ("t_precond_ms", "n_precond"),
+            "k21_gradient": ("t_k21_ms", "n_k21")}
+    allk = {}
+    for k, (tk, nk) in keys.items():
+        tot = float(np.sum([r[tk] for r in reps]))
+        n = int(np.sum([r[nk] for r in reps]))
+        if n == 0:
+            continue
+        avg_ms = tot / n
+        byts = per_node[k] * nodes
+        gbs = byts / (avg_ms * 1e-3) / 1e9
+        allk[k] = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                   "traffic": None, "avg_ms": avg_ms, "launches": n, "bytes_per_launch": byts,
+                   "share_of_step_ms": tot / len(reps)}
+    dom = max(allk, key=lambda k: allk[k]["share_of_step_ms"]) if allk else None
+    d = dict(allk[dom]) if dom else None
+    if d:
+        d["kernel"] = dom
+    return {"dominant": d, "all": allk}
+
+
+def cpu_baseline(pr, n_sample):
+    """The FP64 CPU oracle on a bounded sample: residual and Jacobian blocks of n_sample elements."""
+    import numpy as np
+    import torch
+    from oracle import LineDG, Physics
+    me = pr.mesh
+    ph = Physics(pr.equation, me.dim, gamma=pr.gamma, mu=pr.mu, prandtl=pr.prandtl)
+    orc = LineDG(me.dim, me.p, me.xyz, me.face_nbr, me.nbr_node, me.switch_plus, ph, pr.c11_interior,
+                 pr.c11_dirichlet, pr.source, pr.gD)
+    rng = np.random.default_rng(0)
+    el = np.sort(rng.choice(me.n_elem, size=min(n_sample, me.n_elem), replace=False))
+    orc.residual(pr.U0, elems=el[:2])  # warm-up
+    t0 = time.perf_counter()
+    orc.residual(pr.U0, elems=el)
+    orc.jacobian(pr.U0, elems=el)
+    dt = time.perf_counter() - t0
+    dofs = len(el) * pr.m * me.np_
+    log(f"[bench] cpu oracle: {len(el)} elements residual+Jacobian in {dt:.1f} s")
+    return {"value": dofs / dt, "unit": "DOF/s", "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"residual + Jacobian blocks (K11, K12) of {len(el)} seeded elements of the workload, "
+                      f"{dt:.1f} s"}
 
 
 def log(msg):
@@ -104,6 +170,10 @@ def main():
                      dU_rel_diff_vs_chosen=float((U - U_chosen).abs().max() / U.abs().max()))
 
     last = reps[-1]
+    roof = roofline(pr, reps, chosen_prec)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(pr, args.cpu_sample)
     out = {
         "metric": "residual+Jacobian DOF/s; Newton step time to 1e-8, plain FP64 vs chosen form",
         "value": value,
@@ -115,11 +185,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64 residual/Jacobian; bf16 storage" if chosen_prec == LDG_BF16 else "f64; f32 storage",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"{pr.name}: 3-D Navier-Stokes Taylor-Green, Re={pr.extra['re']:.0f}, "
                                f"M=0.2, p={pr.mesh.p}, {pr.mesh.n_elem} hexes, BDF2 dt={pr.dt}",
-                   "dofs": pr.n_dof},
+                   "dofs": pr.n_dof,
+                   "storage_prec": {0: "f64", 1: "f32", 2: "bf16"}[chosen_prec]},
         "newton": {"chosen": {"ms_per_step": ms_step, "gmres_iters": last["gmres_iters"],
                               "refine_steps": last["refine_steps"], "lin_relres": last["lin_relres"],
                               "newton_res_before": last["newton_res_before"],
@@ -127,6 +198,9 @@ def main():
                               "t_resid_ms": t_res, "t_assemble_ms": t_asm,
                               "t_solve_ms": float(np.mean([r["t_solve_ms"] for r in reps]))},
                    "plain_fp64": plain},
+        "roofline": roof["dominant"],
+        "kernels": roof["all"],
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     ctx.close()

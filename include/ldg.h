@@ -158,6 +158,11 @@ typedef struct {
   double lin_relres;      /* final ||b - (alpha I - gamma A) dU|| / ||b||, exact FP64 operator */
   double newton_res_before, newton_res_after; /* ||G(U)||_2 before / after        */
   double t_resid_ms, t_assemble_ms, t_solve_ms, t_total_ms;
+  /* stream-timed (HIP events) kernels inside the linear solve: the stored
+   * split product y = alpha x - gamma (K11 x + K12 w), the matrix-free
+   * w = K21 x, and the block ILU(0) apply; totals over the step and counts */
+  double t_jacvec_ms, t_k21_ms, t_precond_ms;
+  int32_t n_jacvec, n_k21, n_precond;
 } ldg_solver_report;
 
 /* One Newton step on G(U) = alpha (U - Ucomb) - gamma R(U) (BDF2:

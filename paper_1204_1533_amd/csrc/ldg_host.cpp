@@ -54,9 +54,39 @@ struct ldg_ctx_s {
   double* d_partial = nullptr;
   double* d_h = nullptr;
   int nblk_dot = 0;
+  // optional per-kernel event timing inside ldg_newton_step
+  struct Timed {
+    std::vector<hipEvent_t> ev;  // start/stop pairs
+    size_t used = 0;
+  };
+  bool timing = false;
+  Timed tm[3];  // 0 jacvec, 1 K21 gradient, 2 precond apply
 };
 
 namespace {
+
+// Records a start/stop event pair around a launch when timing is on.
+struct Span {
+  ldg_ctx c;
+  int which;
+  hipEvent_t stop = nullptr;
+  Span(ldg_ctx c_, int w) : c(c_), which(w) {
+    if (!c->timing) return;
+    auto& t = c->tm[which];
+    if (t.used + 2 > t.ev.size()) {
+      hipEvent_t a, b;
+      if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
+      t.ev.push_back(a);
+      t.ev.push_back(b);
+    }
+    hipEventRecord(t.ev[t.used], c->dc.stream);
+    stop = t.ev[t.used + 1];
+    t.used += 2;
+  }
+  ~Span() {
+    if (stop) hipEventRecord(stop, c->dc.stream);
+  }
+};
 
 ldg_status fail(ldg_ctx c, ldg_status s, const std::string& msg) {
   if (c) c->err = msg;
@@ -153,6 +183,8 @@ void ldg_destroy(ldg_ctx c) {
                   c->d_tmp, c->d_Un, c->d_partial, c->d_h};
   for (void* p : ptrs)
     if (p) hipFree(p);
+  for (auto& t : c->tm)
+    for (hipEvent_t e : t.ev) hipEventDestroy(e);
   delete c;
 }
 
@@ -341,12 +373,16 @@ static ldg_status apply_op(ldg_ctx c, const double* x, double* y, bool exact) {
   const DevCtx& dc = c->dc;
   TRY(dev_alloc(c, &c->d_W, (size_t)c->nq));
   const bool vis = dc.EQ != LDG_EULER;
-  if (vis) HIPCK(c, launch_gradient(dc, x, c->d_W, true));
+  if (vis) {
+    Span sp(c, 1);
+    HIPCK(c, launch_gradient(dc, x, c->d_W, true));
+  }
   if (exact) {
     // y = alpha x - gamma dR/dU x  (tangent of the FP64 residual at the assembled state)
     HIPCK(c, launch_residual_tangent(dc, c->d_Ua, x, vis ? c->d_Qa : nullptr, vis ? c->d_W : nullptr, y));
     HIPCK(c, launch_axpby(y, c->alpha, x, -c->gamma, c->ndof, dc.stream));
   } else {
+    Span sp(c, 0);
     HIPCK(c, launch_jacvec(dc, c->d_K11, c->d_K12, c->prec, c->alpha, c->gamma, x, vis ? c->d_W : nullptr, y));
   }
   return LDG_OK;
@@ -431,7 +467,10 @@ static ldg_status gmres(ldg_ctx c, const double* b, double* x, double rtol_abs, 
     for (int k = 0; k < restart; ++k) {
       double* vk = c->d_V + (int64_t)k * n;
       double* w = c->d_V + (int64_t)(k + 1) * n;
-      HIPCK(c, launch_precond_apply(dc, c->d_F, c->prec, vk, c->d_z));
+      {
+        Span sp(c, 2);
+        HIPCK(c, launch_precond_apply(dc, c->d_F, c->prec, vk, c->d_z));
+      }
       TRY(apply_op(c, c->d_z, w, exact));
       // CGS2
       TRY(dots(c, c->d_V, k + 1, w, h.data()));
@@ -520,6 +559,8 @@ ldg_status ldg_newton_step(ldg_ctx c, double* U, const double* Ucomb, double alp
   const int64_t n = c->ndof;
   ldg_solver_report r{};
   TRY(ensure_krylov(c, o->restart));
+  c->timing = rep != nullptr;
+  for (auto& t : c->tm) t.used = 0;
   hipEvent_t ev[5];
   for (auto& e : ev) HIPCK(c, hipEventCreate(&e));
   auto t_start = std::chrono::steady_clock::now();
@@ -615,6 +656,18 @@ ldg_status ldg_newton_step(ldg_ctx c, double* U, const double* Ucomb, double alp
   hipEventElapsedTime(&ms, ev[2], ev[3]);
   r.t_solve_ms = ms;
   r.t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  double* tot[3] = {&r.t_jacvec_ms, &r.t_k21_ms, &r.t_precond_ms};
+  int32_t* cnt[3] = {&r.n_jacvec, &r.n_k21, &r.n_precond};
+  for (int k = 0; k < 3; ++k) {
+    double acc = 0.0;
+    for (size_t i = 0; i + 1 < c->tm[k].used; i += 2) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, c->tm[k].ev[i], c->tm[k].ev[i + 1]) == hipSuccess) acc += t;
+    }
+    *tot[k] = acc;
+    *cnt[k] = (int32_t)(c->tm[k].used / 2);
+  }
+  c->timing = false;
   for (auto& e : ev) hipEventDestroy(e);
   if (rep) *rep = r;
   if (!ok) return fail(c, LDG_E_NOT_CONVERGED, "linear solve did not reach rtol");

@@ -48,6 +48,8 @@ class ldg_solver_report(ctypes.Structure):
         ("newton_res_before", ctypes.c_double), ("newton_res_after", ctypes.c_double),
         ("t_resid_ms", ctypes.c_double), ("t_assemble_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double),
         ("t_total_ms", ctypes.c_double),
+        ("t_jacvec_ms", ctypes.c_double), ("t_k21_ms", ctypes.c_double), ("t_precond_ms", ctypes.c_double),
+        ("n_jacvec", ctypes.c_int32), ("n_k21", ctypes.c_int32), ("n_precond", ctypes.c_int32),
     ]
 
     def as_dict(self):
