@@ -124,7 +124,8 @@ ldg_status ldg_jacobian_assemble(ldg_ctx ctx, const double* U_dev, double alpha,
 ldg_status ldg_jacvec(ldg_ctx ctx, const double* x_dev, double* y_dev, int32_t exact_fp64);
 
 /* z = P^{-1} r with the block ILU(0) factors of A~ (per element, forward and
- * backward block substitution).  r_dev, z_dev [E][m][Np], may not alias.
+ * backward block substitution), plus the learned correction when the current
+ * assembly applies one.  r_dev, z_dev [E][m][Np], may not alias.
  * Error: LDG_E_NOT_ASSEMBLED. */
 ldg_status ldg_precond_apply(ldg_ctx ctx, const double* r_dev, double* z_dev);
 
@@ -179,6 +180,87 @@ ldg_status ldg_newton_step(ldg_ctx ctx, double* U_dev, const double* Ucomb_dev, 
 /* Classical four-stage Runge-Kutta on dU/dt = R(U) (Section 4.1), n_steps
  * steps of size dt, U_dev in/out [E][m][Np]. */
 ldg_status ldg_rk4(ldg_ctx ctx, double* U_dev, double dt, int32_t n_steps);
+
+/* ------------------------------------------------------------------------
+ * Learned correction of the preconditioner (an addition beyond the paper).
+ *
+ * A small network maps, per element, the m x m diagonal blocks D_b of A~ and
+ * the element's Newton residual to Np blocks Y_b; with C_b = Y_b D_b^{-1} the
+ * corrected preconditioner is  z = z0 + C (r - A~ z0),  z0 = ILU(0)^{-1} r,
+ * element by element.  C is evaluated once per assembly, so z is linear in r.
+ * Features of an element (n_in = Np m^2 + Np m floats): D_b / sigma with
+ * sigma = max |entries of all D_b| (index (b m + i) m + j), then
+ * G / max|G| (index Np m^2 + b m + i) with G = -gamma R(U) at the assembly
+ * state (zero if G = 0).  Network: H1 = tanh(X W1 + b1), H2 = tanh(H1 W2 + b2),
+ * Y = H2 W3 + b3.  Parameters (FP32, flat): W1 [n_in][h], b1 [h], W2 [h][h],
+ * b2 [h], W3 [h][n_out], b3 [n_out], n_out = Np m^2.  If any C entry is not
+ * finite the assembly falls back to plain ILU(0) and reports it.
+ * ---------------------------------------------------------------------- */
+typedef struct ldg_net_s* ldg_net;
+
+/* Training samples (device, FP32), one row per sampled element and K probes v:
+ *  X [n][n_in] features;  A [n][Np][Dp+1][m][m] the rows of A~ on the line
+ *  pattern (slot order as in ldg_export_operators);  S [n][K][Np][m] the
+ *  defect s = v - A~ ILU^{-1} v and T [n][K][Np][m] t = D_b^{-1} s_b, both
+ *  divided by the element norm of v (zero if that norm is zero).
+ * Loss:  L = 1/(n K) sum ||s - A~ (Y t)||^2  (Y_b applied node by node). */
+typedef struct {
+  int64_t n;
+  int32_t n_probe;
+  const float* X_dev;
+  const float* A_dev;
+  const float* S_dev;
+  const float* T_dev;
+} ldg_sample_batch;
+
+/* Create a network for elements of dimension dim, degree p and m components,
+ * hidden width `hidden`.  W1, W2 are Glorot-uniform from a splitmix64 stream
+ * seeded by `seed`; W3 and every bias start at zero (so the correction starts
+ * as plain ILU(0)).  Adam state starts at zero.
+ * Errors: LDG_E_INVALID, LDG_E_NOMEM. */
+ldg_status ldg_net_create(int32_t dim, int32_t p, int32_t m, int32_t hidden, uint64_t seed, void* hip_stream,
+                          ldg_net* out);
+void ldg_net_destroy(ldg_net net);
+/* Number of parameters, or -1 for NULL. */
+int64_t ldg_net_num_params(ldg_net net);
+/* Copy all parameters in (resets the Adam state) or out, flat FP32 device arrays. */
+ldg_status ldg_net_set_params(ldg_net net, const float* params_dev);
+ldg_status ldg_net_get_params(ldg_net net, float* params_dev);
+/* Y [n][n_out] = network(X [n][n_in]); prec LDG_F32 (FP32 operands) or
+ * LDG_BF16 (features, weights and hidden activations rounded to BF16, FP32
+ * accumulation), both on matrix cores. */
+ldg_status ldg_net_forward(ldg_net net, const float* X_dev, int64_t n, int32_t prec, float* Y_dev);
+/* Loss of a batch and its gradient with respect to every parameter (kept for
+ * ldg_net_adam_step, and copied to grad_dev [n_params] when not NULL); *loss
+ * (host) receives L.  In LDG_BF16 mode the operands of every product are
+ * BF16 (activation gradients too), accumulation and the loss are FP32. */
+ldg_status ldg_net_loss_grad(ldg_net net, const ldg_sample_batch* batch, int32_t prec, float* grad_dev,
+                             double* loss);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias corrected) with the
+ * gradient of the last ldg_net_loss_grad; refreshes the BF16 weights. */
+ldg_status ldg_net_adam_step(ldg_net net, double lr);
+const char* ldg_net_last_error(ldg_net net);
+
+/* Attach a network to a context (NULL detaches); it must have been created
+ * for the context's dim, p and m.  infer_prec (LDG_F32 / LDG_BF16) is the
+ * precision of its evaluation at assembly.  Attaching enables the correction
+ * for ldg_jacobian_assemble; ldg_newton_step enables it per call from
+ * opts.use_learned.  Errors: LDG_E_SHAPE, LDG_E_UNSUPPORTED (element too
+ * large for the training kernel: Np > 128). */
+ldg_status ldg_learned_attach(ldg_ctx ctx, ldg_net net, int32_t infer_prec);
+/* on != 0: keep A~, the features and D^{-1} at every assembly so that
+ * ldg_learned_samples can read them (also without a network). */
+ldg_status ldg_learned_collect(ldg_ctx ctx, int32_t on);
+/* 1 if the current assembly applies the correction, 0 otherwise. */
+int32_t ldg_learned_active(ldg_ctx ctx);
+/* Training samples from the current assembly for the elements
+ * elems_host[0..n): probes V_dev [K][E][m][Np] (device, FP64), or NULL to use
+ * the first K Arnoldi vectors of the last GMRES cycle.  Outputs as in
+ * ldg_sample_batch.  Errors: LDG_E_NOT_ASSEMBLED (no assembly kept A~),
+ * LDG_E_INVALID (element out of range, K larger than the Arnoldi vectors
+ * available). */
+ldg_status ldg_learned_samples(ldg_ctx ctx, const int64_t* elems_host, int64_t n, const double* V_dev, int32_t K,
+                               float* X_dev, float* A_dev, float* S_dev, float* T_dev);
 
 const char* ldg_status_string(ldg_status s);
 const char* ldg_last_error(ldg_ctx ctx);

@@ -28,23 +28,6 @@
 
 namespace ldg {
 
-// column node of line slot `slot` for row node a (within the element)
-template <int D, int P>
-__device__ __forceinline__ int slot_col(int a, int slot) {
-  constexpr int N1 = P + 1;
-  if (slot < N1) return line_node<D, N1>(0, a / N1, slot);
-  const int n = 1 + (slot - N1) / P, r = (slot - N1) % P;
-  int l, t;
-  node_line<N1>(a, n, l, t);
-  return line_node<D, N1>(n, l, r < t ? r : r + 1);
-}
-template <int N1>
-__device__ __forceinline__ int slot_of(int n, int t, int tp, int self) {
-  // slot of column position tp on the row's direction-n line; the row sits at t
-  if (tp == t) return self;
-  return n == 0 ? tp : N1 + (n - 1) * (N1 - 1) + (tp < t ? tp : tp - 1);
-}
-
 // --------------------------------------------------------------------------- jacvec
 template <int D, int P, int EQ, int PR>
 __global__ void __launch_bounds__(256) jacvec_kernel(MeshParams mp, const void* __restrict__ K11,
@@ -528,10 +511,16 @@ __global__ void convert_kernel(const void* __restrict__ in, void* __restrict__ o
     Store<POUT>::put(out, i, Store<PIN>::get(in, i));
 }
 
+static unsigned copy_grid(int64_t n) {
+  const int64_t g = (n + 255) / 256;
+  return (unsigned)(g > 65536 ? 65536 : g);
+}
+
+// At_copy (optional) receives A~ in FP32 before it is factorised.
 // F holds the factors in storage precision fprec.  For fprec = BF16 the
 // factorisation runs on an FP32 copy placed after the BF16 factors in F.
 hipError_t launch_precond_factor(const DevCtx& dc, const void* K11, const void* K12, int prec, double alpha,
-                                 double gamma, void* F, int fprec) {
+                                 double gamma, void* F, int fprec, float* At_copy) {
   const int64_t NN = dc.E * dc.NP;
   const int64_t nF = NN * (int64_t)(dc.D * dc.P + 1) * dc.M * dc.M;
   LDG_DISPATCH(dc, {
@@ -543,6 +532,9 @@ hipError_t launch_precond_factor(const DevCtx& dc, const void* K11, const void* 
         if (bytes > 65536) hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         hipLaunchKernelGGL(k, dim3((unsigned)dc.E), dim3(NT_ELEM), bytes, dc.stream, dc.ops, dc.mp, K11, K12, alpha,
                            gamma, F);
+        if (At_copy)
+          hipLaunchKernelGGL((convert_kernel<PREC_F64, PREC_F32>), dim3(copy_grid(nF)), dim3(256), 0, dc.stream, F,
+                             At_copy, nF);
         hipLaunchKernelGGL((factor_kernel<D, P, EQ, PREC_F64>), dim3((unsigned)dc.E), dim3(64), 0, dc.stream, dc.E,
                            F);
       } else {
@@ -551,6 +543,9 @@ hipError_t launch_precond_factor(const DevCtx& dc, const void* K11, const void* 
         if (bytes > 65536) hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         hipLaunchKernelGGL(k, dim3((unsigned)dc.E), dim3(NT_ELEM), bytes, dc.stream, dc.ops, dc.mp, K11, K12, alpha,
                            gamma, work);
+        if (At_copy)
+          hipLaunchKernelGGL((convert_kernel<PREC_F32, PREC_F32>), dim3(copy_grid(nF)), dim3(256), 0, dc.stream, work,
+                             At_copy, nF);
         hipLaunchKernelGGL((factor_kernel<D, P, EQ, PREC_F32>), dim3((unsigned)dc.E), dim3(64), 0, dc.stream, dc.E,
                            work);
         if (fprec == PREC_BF16) {

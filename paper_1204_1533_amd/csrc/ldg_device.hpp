@@ -60,6 +60,27 @@ __device__ __forceinline__ void node_line(int node, int n, int& l, int& t) {
   l = (node % s) + (node / (s * N1)) * s;
 }
 
+// ---------------------------------------------------------------- line-pattern slots
+// A row node a has D p + 1 line-pattern columns: slots 0..p are the nodes of its
+// direction-0 line by position (its own position is the diagonal slot); then,
+// for each further direction n, p slots for the other nodes of its direction-n line.
+// column node of line slot `slot` for row node a (within the element)
+template <int D, int P>
+__device__ __forceinline__ int slot_col(int a, int slot) {
+  constexpr int N1 = P + 1;
+  if (slot < N1) return line_node<D, N1>(0, a / N1, slot);
+  const int n = 1 + (slot - N1) / P, r = (slot - N1) % P;
+  int l, t;
+  node_line<N1>(a, n, l, t);
+  return line_node<D, N1>(n, l, r < t ? r : r + 1);
+}
+template <int N1>
+__device__ __forceinline__ int slot_of(int n, int t, int tp, int self) {
+  // slot of column position tp on the row's direction-n line; the row sits at t
+  if (tp == t) return self;
+  return n == 0 ? tp : N1 + (n - 1) * (N1 - 1) + (tp < t ? tp : tp - 1);
+}
+
 // ---------------------------------------------------------------- dual numbers
 template <int K>
 struct Dual {

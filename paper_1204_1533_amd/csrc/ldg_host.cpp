@@ -10,7 +10,7 @@
 #include <vector>
 
 #include "../../include/ldg.h"
-#include "ldg_kernels.hpp"
+#include "ldg_ctx.hpp"
 
 namespace ldg {
 bool build_line_ops(int p, int node_family, LineOps& ops, std::vector<double>* nodes_out);
@@ -18,119 +18,7 @@ bool build_line_ops(int p, int node_family, LineOps& ops, std::vector<double>* n
 
 using namespace ldg;
 
-struct ldg_ctx_s {
-  DevCtx dc{};
-  std::string err;
-  int64_t ndof = 0, nq = 0, nnode = 0;
-  double* d_xyz = nullptr;
-  int64_t* d_face_nbr = nullptr;
-  int32_t* d_nbr_node = nullptr;
-  int8_t* d_sw = nullptr;
-  double* d_gD = nullptr;
-  double* d_S = nullptr;
-  double* d_Q = nullptr;   // Q scratch (residual)
-  double* d_W = nullptr;   // K21 x scratch
-  double* d_W2 = nullptr;  // tangent Q scratch
-  // assembled state
-  bool assembled = false;
-  int prec = 0;
-  double alpha = 1.0, gamma = 0.0;
-  void* d_K11 = nullptr;
-  void* d_K12 = nullptr;
-  void* d_F = nullptr;
-  size_t capK11 = 0, capK12 = 0, capF = 0;
-  double* d_Ua = nullptr;  // state at assembly
-  double* d_Qa = nullptr;  // D(U) at assembly
-  // Newton / Krylov workspace
-  double* d_V = nullptr;
-  int cap_restart = 0;
-  double* d_R = nullptr;
-  double* d_G = nullptr;
-  double* d_x = nullptr;
-  double* d_r = nullptr;
-  double* d_z = nullptr;
-  double* d_tmp = nullptr;
-  double* d_Un = nullptr;
-  double* d_partial = nullptr;
-  double* d_h = nullptr;
-  int nblk_dot = 0;
-  // optional per-kernel event timing inside ldg_newton_step
-  struct Timed {
-    std::vector<hipEvent_t> ev;  // start/stop pairs
-    size_t used = 0;
-  };
-  bool timing = false;
-  Timed tm[3];  // 0 jacvec, 1 K21 gradient, 2 precond apply
-};
-
 namespace {
-
-// Records a start/stop event pair around a launch when timing is on.
-struct Span {
-  ldg_ctx c;
-  int which;
-  hipEvent_t stop = nullptr;
-  Span(ldg_ctx c_, int w) : c(c_), which(w) {
-    if (!c->timing) return;
-    auto& t = c->tm[which];
-    if (t.used + 2 > t.ev.size()) {
-      hipEvent_t a, b;
-      if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
-      t.ev.push_back(a);
-      t.ev.push_back(b);
-    }
-    hipEventRecord(t.ev[t.used], c->dc.stream);
-    stop = t.ev[t.used + 1];
-    t.used += 2;
-  }
-  ~Span() {
-    if (stop) hipEventRecord(stop, c->dc.stream);
-  }
-};
-
-ldg_status fail(ldg_ctx c, ldg_status s, const std::string& msg) {
-  if (c) c->err = msg;
-  return s;
-}
-
-#define HIPCK(ctx, call)                                                                  \
-  do {                                                                                    \
-    hipError_t e_ = (call);                                                               \
-    if (e_ != hipSuccess) return fail(ctx, LDG_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
-  } while (0)
-
-template <class T>
-ldg_status dev_alloc(ldg_ctx c, T** p, size_t count) {
-  if (*p) return LDG_OK;
-  if (count == 0) count = 1;
-  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
-  if (e != hipSuccess) {
-    *p = nullptr;
-    return fail(c, LDG_E_NOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
-  }
-  return LDG_OK;
-}
-
-ldg_status grow(ldg_ctx c, void** p, size_t* cap, size_t bytes) {
-  if (*cap >= bytes && *p) return LDG_OK;
-  if (*p) hipFree(*p);
-  *p = nullptr;
-  *cap = 0;
-  if (hipMalloc(p, bytes) != hipSuccess) {
-    *p = nullptr;
-    return fail(c, LDG_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
-  }
-  *cap = bytes;
-  return LDG_OK;
-}
-
-size_t elem_size(int prec) { return prec == LDG_F64 ? 8 : (prec == LDG_F32 ? 4 : 2); }
-
-#define TRY(x)                     \
-  do {                             \
-    ldg_status s_ = (x);           \
-    if (s_ != LDG_OK) return s_;   \
-  } while (0)
 
 int64_t ipow64(int64_t b, int e) {
   int64_t r = 1;
@@ -183,6 +71,7 @@ void ldg_destroy(ldg_ctx c) {
                   c->d_tmp, c->d_Un, c->d_partial, c->d_h};
   for (void* p : ptrs)
     if (p) hipFree(p);
+  learned_free(c);
   for (auto& t : c->tm)
     for (hipEvent_t e : t.ev) hipEventDestroy(e);
   delete c;
@@ -340,7 +229,9 @@ ldg_status ldg_residual(ldg_ctx c, const double* U, double* R, double* Q) {
   return LDG_OK;
 }
 
-ldg_status ldg_jacobian_assemble(ldg_ctx c, const double* U, double alpha, double gamma, int32_t prec) {
+// R_at_U: the residual at U when the caller has it (features of the learned correction)
+static ldg_status assemble(ldg_ctx c, const double* U, double alpha, double gamma, int32_t prec,
+                           const double* R_at_U) {
   if (!c) return LDG_E_INVALID;
   if (!U) return fail(c, LDG_E_INVALID, "null pointer");
   if (prec < 0 || prec > 2) return fail(c, LDG_E_INVALID, "storage_prec");
@@ -361,12 +252,21 @@ ldg_status ldg_jacobian_assemble(ldg_ctx c, const double* U, double alpha, doubl
   const bool vis = dc.EQ != LDG_EULER;
   if (vis) HIPCK(c, launch_gradient(dc, U, c->d_Qa, false));
   HIPCK(c, launch_jacobian(dc, U, vis ? c->d_Qa : nullptr, c->d_K11, c->d_K12, prec));
-  HIPCK(c, launch_precond_factor(dc, c->d_K11, c->d_K12, prec, alpha, gamma, c->d_F, fprec));
+  const bool keep = c->learned_collect || (c->net && c->learned_enabled);
+  if (keep) TRY(dev_alloc(c, &c->d_At, nF));
+  c->learned_kept = keep;
+  c->learned_active = false;
+  HIPCK(c, launch_precond_factor(dc, c->d_K11, c->d_K12, prec, alpha, gamma, c->d_F, fprec, keep ? c->d_At : nullptr));
   c->assembled = true;
   c->prec = prec;
   c->alpha = alpha;
   c->gamma = gamma;
+  TRY(learned_after_form(c, R_at_U, gamma));
   return LDG_OK;
+}
+
+ldg_status ldg_jacobian_assemble(ldg_ctx c, const double* U, double alpha, double gamma, int32_t prec) {
+  return assemble(c, U, alpha, gamma, prec, nullptr);
 }
 
 static ldg_status apply_op(ldg_ctx c, const double* x, double* y, bool exact) {
@@ -401,8 +301,7 @@ ldg_status ldg_precond_apply(ldg_ctx c, const double* r, double* z) {
   if (!r || !z) return fail(c, LDG_E_INVALID, "null pointer");
   if ((const void*)r == (const void*)z) return fail(c, LDG_E_INVALID, "r and z alias");
   if (!c->assembled) return fail(c, LDG_E_NOT_ASSEMBLED, "call ldg_jacobian_assemble first");
-  HIPCK(c, launch_precond_apply(c->dc, c->d_F, c->prec, r, z));
-  return LDG_OK;
+  return precond_apply_any(c, r, z);
 }
 
 ldg_status ldg_export_operators(ldg_ctx c, double* K11, double* K12, double* F) {
@@ -469,7 +368,7 @@ static ldg_status gmres(ldg_ctx c, const double* b, double* x, double rtol_abs, 
       double* w = c->d_V + (int64_t)(k + 1) * n;
       {
         Span sp(c, 2);
-        HIPCK(c, launch_precond_apply(dc, c->d_F, c->prec, vk, c->d_z));
+        TRY(precond_apply_any(c, vk, c->d_z));
       }
       TRY(apply_op(c, c->d_z, w, exact));
       // CGS2
@@ -502,6 +401,7 @@ static ldg_status gmres(ldg_ctx c, const double* b, double* x, double rtol_abs, 
       *est_res = std::fabs(g[k + 1]);
       if (std::fabs(g[k + 1]) <= rtol_abs || its >= max_iters || hn == 0.0) break;
     }
+    c->krylov_avail = k_used;
     for (int i = k_used - 1; i >= 0; --i) {
       double s = g[i];
       for (int j = i + 1; j < k_used; ++j) s -= H[i * restart + j] * y[j];
@@ -511,7 +411,7 @@ static ldg_status gmres(ldg_ctx c, const double* b, double* x, double rtol_abs, 
     HIPCK(c, hipMemcpyAsync(c->d_h, y.data(), sizeof(double) * k_used, hipMemcpyHostToDevice, dc.stream));
     HIPCK(c, hipMemsetAsync(c->d_tmp, 0, sizeof(double) * n, dc.stream));
     HIPCK(c, launch_lincomb(c->d_tmp, c->d_V, n, k_used, c->d_h, n, dc.stream));
-    HIPCK(c, launch_precond_apply(dc, c->d_F, c->prec, c->d_tmp, c->d_z));
+    TRY(precond_apply_any(c, c->d_tmp, c->d_z));
     HIPCK(c, launch_axpby(x, 1.0, c->d_z, 1.0, n, dc.stream));
     if (*est_res <= rtol_abs || its >= max_iters) {
       // true residual for the report
@@ -555,6 +455,7 @@ ldg_status ldg_newton_step(ldg_ctx c, double* U, const double* Ucomb, double alp
   if (!U || !o) return fail(c, LDG_E_INVALID, "null pointer");
   if (o->rtol <= 0 || o->max_iters < 1 || o->storage_prec < 0 || o->storage_prec > 2)
     return fail(c, LDG_E_INVALID, "solver options");
+  if (o->use_learned && !c->net) return fail(c, LDG_E_INVALID, "use_learned without an attached network");
   const DevCtx& dc = c->dc;
   const int64_t n = c->ndof;
   ldg_solver_report r{};
@@ -577,7 +478,11 @@ ldg_status ldg_newton_step(ldg_ctx c, double* U, const double* Ucomb, double alp
   if (!std::isfinite(g0)) return fail(c, LDG_E_NONFINITE, "non-finite Newton residual");
   const bool reassemble = o->reassemble || !c->assembled || c->alpha != alpha || c->gamma != gamma ||
                           c->prec != o->storage_prec;
-  if (reassemble) TRY(ldg_jacobian_assemble(c, U, alpha, gamma, o->storage_prec));
+  if (reassemble) {
+    c->learned_enabled = c->net && o->use_learned;
+    TRY(assemble(c, U, alpha, gamma, o->storage_prec, c->d_R));
+  }
+  r.fallback_used = c->learned_fallback;
   HIPCK(c, hipEventRecord(ev[2], dc.stream));
   // b = -G  (kept in d_G)
   HIPCK(c, launch_axpby(c->d_G, 0.0, c->d_G, -1.0, n, dc.stream));

@@ -42,7 +42,7 @@ hipError_t launch_jacvec(const DevCtx& c, const void* K11, const void* K12, int 
 // Preconditioner A~ (line pattern) formed from the stored K11/K12 and the
 // K21 weights, then factorised by block ILU(0); factors [slot][c][c'][E*Np].
 hipError_t launch_precond_factor(const DevCtx& c, const void* K11, const void* K12, int prec, double alpha,
-                                 double gamma, void* F, int fprec);
+                                 double gamma, void* F, int fprec, float* At_copy = nullptr);
 hipError_t launch_precond_apply(const DevCtx& c, const void* F, int fprec, const double* r, double* z);
 
 // Conversions of the internal layouts to the FP64 exchange layouts of ldg.h.
@@ -59,5 +59,29 @@ hipError_t launch_lincomb(double* y, const double* V, int64_t ldv, int k, const 
                           hipStream_t s);  // y += V coef
 hipError_t launch_rk4_stage(double* Ustage, const double* U, const double* K, double a, double* Acc, double b,
                             int64_t n, hipStream_t s);
+
+// Learned correction (k_learned.hip) and the network kernels (k_mlp.hip).
+int learned_supported(const DevCtx& c);
+hipError_t launch_learned_features(const DevCtx& c, const float* At, const double* R, double gscale, float* X,
+                                   uint16_t* Xb, float* Dinv);
+hipError_t launch_learned_cblocks(const DevCtx& c, const float* Y, const float* Dinv, float* C, int* bad);
+hipError_t launch_learned_apply(const DevCtx& c, const float* At, const float* C, const double* r, const double* z0,
+                                double* z);
+hipError_t launch_learned_samples(const DevCtx& c, const int64_t* elems, int64_t n, int K, const float* At,
+                                  const float* Xf, const float* Dinv, const double* V, const double* Z0, int64_t ndof,
+                                  float* Xs, float* As, float* S, float* T);
+hipError_t launch_learned_loss(const DevCtx& c, int64_t n, int K, const float* As, const float* S, const float* T,
+                               const float* Y, float scale, float* dY, double* loss_part);
+hipError_t launch_gemm_bf16(int M, int N, int K, const uint16_t* A, int64_t sam, int64_t sak, const uint16_t* B,
+                            int64_t sbk, int64_t sbn, float* C, int64_t ldc, uint16_t* Cb, const float* bias,
+                            int epilogue, float beta, hipStream_t s);
+hipError_t launch_gemm_f32(int M, int N, int K, const float* A, int64_t sam, int64_t sak, const float* B, int64_t sbk,
+                           int64_t sbn, float* C, int64_t ldc, uint16_t* Cb, const float* bias, int epilogue,
+                           float beta, hipStream_t s);
+hipError_t launch_tanh_backward(const float* dH, const float* H, float* dA, uint16_t* dAb, int64_t n, hipStream_t s);
+hipError_t launch_colsum(const float* X, int M, int N, float* out, hipStream_t s);
+hipError_t launch_adam(float* w, uint16_t* wb, const float* g, float* m1, float* m2, int64_t n, float lr, float b1,
+                       float b2, float eps, int step, hipStream_t s);
+hipError_t launch_to_bf16(const float* x, uint16_t* y, int64_t n, hipStream_t s);
 
 }  // namespace ldg

@@ -56,6 +56,11 @@ class ldg_solver_report(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ldg_sample_batch(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("n_probe", ctypes.c_int32), ("X_dev", ctypes.c_void_p),
+                ("A_dev", ctypes.c_void_p), ("S_dev", ctypes.c_void_p), ("T_dev", ctypes.c_void_p)]
+
+
 _P = ctypes.c_void_p
 _SIGS = {
     "ldg_create": (ctypes.c_int, [ctypes.POINTER(ldg_problem_desc), _P, ctypes.POINTER(_P)]),
@@ -74,6 +79,21 @@ _SIGS = {
     "ldg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "ldg_last_error": (ctypes.c_char_p, [_P]),
     "ldg_num_dofs": (ctypes.c_int64, [_P]),
+    "ldg_net_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
+                                      _P, ctypes.POINTER(_P)]),
+    "ldg_net_destroy": (None, [_P]),
+    "ldg_net_num_params": (ctypes.c_int64, [_P]),
+    "ldg_net_set_params": (ctypes.c_int, [_P, _P]),
+    "ldg_net_get_params": (ctypes.c_int, [_P, _P]),
+    "ldg_net_forward": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int32, _P]),
+    "ldg_net_loss_grad": (ctypes.c_int, [_P, ctypes.POINTER(ldg_sample_batch), ctypes.c_int32, _P,
+                                         ctypes.POINTER(ctypes.c_double)]),
+    "ldg_net_adam_step": (ctypes.c_int, [_P, ctypes.c_double]),
+    "ldg_net_last_error": (ctypes.c_char_p, [_P]),
+    "ldg_learned_attach": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
+    "ldg_learned_collect": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "ldg_learned_active": (ctypes.c_int32, [_P]),
+    "ldg_learned_samples": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, ctypes.c_int32, _P, _P, _P, _P]),
 }
 
 _lib = None
@@ -207,7 +227,75 @@ class Context:
     def ldg_num_dofs(self):
         return int(self.lib.ldg_num_dofs(self.h))
 
+    def ldg_learned_attach(self, net, infer_prec=LDG_BF16):
+        self._net = net
+        self._check(self.lib.ldg_learned_attach(self.h, net.h if net is not None else None, int(infer_prec)))
+
+    def ldg_learned_collect(self, on=True):
+        self._check(self.lib.ldg_learned_collect(self.h, int(on)))
+
+    def ldg_learned_active(self):
+        return int(self.lib.ldg_learned_active(self.h))
+
+    def ldg_learned_samples(self, elems, V, K, X, A, S, T):
+        el = np.ascontiguousarray(elems, dtype=np.int64)
+        self._check(self.lib.ldg_learned_samples(self.h, el.ctypes.data, len(el), _ptr(V), int(K), _ptr(X), _ptr(A),
+                                                 _ptr(S), _ptr(T)))
+
     # sizes of the exchange layouts
     def nslots(self):
         D, p = self.dim, self.p
         return D * p + 1 + 2 * D, D * p + 1 + D, D * p + 1
+
+
+class Net:
+    """Owns one ldg_net (the learned preconditioner correction's network)."""
+
+    def __init__(self, dim, p, m, hidden=256, seed=0, stream=None):
+        lib = load_library()
+        self.lib = lib
+        h = _P()
+        st = lib.ldg_net_create(int(dim), int(p), int(m), int(hidden), int(seed), stream, ctypes.byref(h))
+        if st != LDG_OK:
+            raise LDGError(st, lib.ldg_status_string(st).decode())
+        self.h = h
+        self.dim, self.p, self.m, self.hidden = dim, p, m, hidden
+        self.np_ = (p + 1) ** dim
+        self.n_in = self.np_ * m * m + self.np_ * m
+        self.n_out = self.np_ * m * m
+
+    def _check(self, st):
+        if st != LDG_OK:
+            raise LDGError(st, self.lib.ldg_net_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ldg_net_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def ldg_net_num_params(self):
+        return int(self.lib.ldg_net_num_params(self.h))
+
+    def ldg_net_set_params(self, params):
+        self._check(self.lib.ldg_net_set_params(self.h, _ptr(params)))
+
+    def ldg_net_get_params(self, params):
+        self._check(self.lib.ldg_net_get_params(self.h, _ptr(params)))
+
+    def ldg_net_forward(self, X, n, prec, Y):
+        self._check(self.lib.ldg_net_forward(self.h, _ptr(X), int(n), int(prec), _ptr(Y)))
+
+    def ldg_net_loss_grad(self, X, A, S, T, n, n_probe, prec=LDG_BF16, grad=None):
+        b = ldg_sample_batch(int(n), int(n_probe), _ptr(X), _ptr(A), _ptr(S), _ptr(T))
+        loss = ctypes.c_double()
+        self._check(self.lib.ldg_net_loss_grad(self.h, ctypes.byref(b), int(prec), _ptr(grad), ctypes.byref(loss)))
+        return loss.value
+
+    def ldg_net_adam_step(self, lr):
+        self._check(self.lib.ldg_net_adam_step(self.h, float(lr)))

@@ -100,3 +100,23 @@ def test_null_context_calls(lib):
     assert lib.ldg_residual(None, None, None, None) == ldg.LDG_E_INVALID
     assert lib.ldg_num_dofs(None) == -1
     assert lib.ldg_status_string(ldg.LDG_E_NOT_ASSEMBLED) == b"operators not assembled"
+
+
+def test_learned_entry_points_validate_before_device_work(lib):
+    """Network and learned-correction calls reject bad arguments without touching a GPU."""
+    from paper_1204_1533_amd import ldg
+    h = ctypes.c_void_p()
+    assert lib.ldg_net_create(4, 3, 5, 256, 0, None, ctypes.byref(h)) == ldg.LDG_E_INVALID
+    assert lib.ldg_net_create(3, 3, 4, 256, 0, None, ctypes.byref(h)) == ldg.LDG_E_INVALID  # m must be 1 or dim+2
+    assert lib.ldg_net_create(3, 0, 5, 256, 0, None, ctypes.byref(h)) == ldg.LDG_E_INVALID
+    assert lib.ldg_net_create(3, 3, 5, 0, 0, None, ctypes.byref(h)) == ldg.LDG_E_INVALID
+    assert not h.value
+    assert lib.ldg_net_num_params(None) == -1
+    assert lib.ldg_net_set_params(None, None) == ldg.LDG_E_INVALID
+    assert lib.ldg_net_adam_step(None, 1e-3) == ldg.LDG_E_INVALID
+    assert lib.ldg_learned_attach(None, None, ldg.LDG_BF16) == ldg.LDG_E_INVALID
+    assert lib.ldg_learned_collect(None, 1) == ldg.LDG_E_INVALID
+    assert lib.ldg_learned_active(None) == 0
+    el = (ctypes.c_int64 * 1)(0)
+    assert lib.ldg_learned_samples(None, el, 1, None, 1, None, None, None, None) == ldg.LDG_E_INVALID
+    lib.ldg_net_destroy(None)
