@@ -45,7 +45,9 @@ __global__ void __launch_bounds__(256) jacvec_kernel(MeshParams mp, const void* 
   double acc[M];
 #pragma unroll
   for (int c = 0; c < M; ++c) acc[c] = 0.0;
-#pragma unroll
+  // slot loops are not unrolled: unrolled, every block load is hoisted and the
+  // kernel spills and drops to one wavefront per SIMD
+#pragma unroll 1
   for (int s = 0; s < NS11; ++s) {
     int64_t col;
     if (s < NSL) {
@@ -68,7 +70,7 @@ __global__ void __launch_bounds__(256) jacvec_kernel(MeshParams mp, const void* 
       for (int k = 0; k < M; ++k) acc[c] += Store<PR>::get(K11, ((int64_t)(s * M + c) * M + k) * NN + gn) * xv[k];
   }
   if constexpr (VIS) {
-#pragma unroll
+#pragma unroll 1
     for (int s = 0; s < NS12; ++s) {
       int64_t col;
       if (s < NSL) {
@@ -426,13 +428,14 @@ template <int D, int P, int EQ, int FP>
 __global__ void __launch_bounds__(64) apply_kernel(int64_t E, const void* __restrict__ F, const double* __restrict__ r,
                                                    double* __restrict__ z) {
   constexpr int N1 = P + 1, NP = ipow(N1, D), M = Eq<D, EQ>::M;
-  constexpr int RPP = 64 / M;
+  constexpr int RPP = 64 / M, NSLMM = (D * P + 1) * M * M;
+  // F: element-major copy of the factors, [E Np][slot][c][c'] (one element's
+  // factors are contiguous, so a workgroup reads whole cache lines)
   __shared__ int rows[NP];
   __shared__ int off[D * P + 2];
   __shared__ double sy[NP * M];
   __shared__ double st[NP * M];
   const int64_t e = blockIdx.x;
-  const int64_t NN = E * NP;
   const int lane = threadIdx.x;
   if (lane == 0) level_table<D, P>(rows, off);
   for (int i = lane; i < NP * M; i += 64) sy[i] = r[e * M * NP + (i % M) * NP + i / M];
@@ -457,7 +460,7 @@ __global__ void __launch_bounds__(64) apply_kernel(int64_t E, const void* __rest
             const int k = line_node<D, N1>(n, l, tk);
             const int s = slot_of<N1>(n, ti, tk, self_i);
 #pragma unroll
-            for (int q = 0; q < M; ++q) acc -= Store<FP>::get(F, ((int64_t)(s * M + c) * M + q) * NN + gi) * sy[k * M + q];
+            for (int q = 0; q < M; ++q) acc -= Store<FP>::get(F, gi * NSLMM + (s * M + c) * M + q) * sy[k * M + q];
           }
         }
       }
@@ -485,7 +488,7 @@ __global__ void __launch_bounds__(64) apply_kernel(int64_t E, const void* __rest
             const int j = line_node<D, N1>(n, l, tj);
             const int s = slot_of<N1>(n, ti, tj, self_i);
 #pragma unroll
-            for (int q = 0; q < M; ++q) acc -= Store<FP>::get(F, ((int64_t)(s * M + c) * M + q) * NN + gi) * sy[j * M + q];
+            for (int q = 0; q < M; ++q) acc -= Store<FP>::get(F, gi * NSLMM + (s * M + c) * M + q) * sy[j * M + q];
           }
         }
         st[i * M + c] = acc;
@@ -496,7 +499,7 @@ __global__ void __launch_bounds__(64) apply_kernel(int64_t E, const void* __rest
         const int self_i = i % N1;
         double v = 0.0;
 #pragma unroll
-        for (int q = 0; q < M; ++q) v += Store<FP>::get(F, ((int64_t)(self_i * M + c) * M + q) * NN + gi) * st[i * M + q];
+        for (int q = 0; q < M; ++q) v += Store<FP>::get(F, gi * NSLMM + (self_i * M + c) * M + q) * st[i * M + q];
         sy[i * M + c] = v;
       }
       __syncthreads();
@@ -509,6 +512,17 @@ template <int PIN, int POUT>
 __global__ void convert_kernel(const void* __restrict__ in, void* __restrict__ out, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     Store<POUT>::put(out, i, Store<PIN>::get(in, i));
+}
+
+// node-fastest [q][E Np] -> element-major [E Np][q], q = (slot, c, c')
+template <int PR>
+__global__ void relayout_kernel(const void* __restrict__ in, void* __restrict__ out, int64_t NN, int nq) {
+  const int64_t n = NN * nq;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t gn = i / nq;
+    const int q = (int)(i % nq);
+    Store<PR>::put(out, i, Store<PR>::get(in, (int64_t)q * NN + gn));
+  }
 }
 
 static unsigned copy_grid(int64_t n) {
@@ -560,6 +574,16 @@ hipError_t launch_precond_factor(const DevCtx& dc, const void* K11, const void* 
   })
 }
 
+hipError_t launch_precond_relayout(const DevCtx& dc, const void* F, int fprec, void* Fem) {
+  const int64_t NN = dc.E * dc.NP;
+  const int nq = (dc.D * dc.P + 1) * dc.M * dc.M;
+  LDG_PREC_DISPATCH(fprec, {
+    hipLaunchKernelGGL((relayout_kernel<PR>), dim3(copy_grid(NN * nq)), dim3(256), 0, dc.stream, F, Fem, NN, nq);
+    return hipGetLastError();
+  })
+}
+
+// Fem: the element-major copy written by launch_precond_relayout.
 hipError_t launch_precond_apply(const DevCtx& dc, const void* F, int fprec, const double* r, double* z) {
   LDG_DISPATCH(dc, {
     LDG_PREC_DISPATCH(fprec, {

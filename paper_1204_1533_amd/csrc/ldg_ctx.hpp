@@ -31,6 +31,8 @@ struct ldg_ctx_s {
   void* d_K11 = nullptr;
   void* d_K12 = nullptr;
   void* d_F = nullptr;
+  void* d_Fem = nullptr;  // element-major copy of the factors (read by the apply)
+  size_t capFem = 0;
   size_t capK11 = 0, capK12 = 0, capF = 0;
   double* d_Ua = nullptr;  // state at assembly
   double* d_Qa = nullptr;  // D(U) at assembly

@@ -67,7 +67,7 @@ int64_t ldg_num_dofs(ldg_ctx ctx) { return ctx ? ctx->ndof : -1; }
 void ldg_destroy(ldg_ctx c) {
   if (!c) return;
   void* ptrs[] = {c->d_xyz, c->d_face_nbr, c->d_nbr_node, c->d_sw, c->d_gD, c->d_S, c->d_Q, c->d_W, c->d_W2,
-                  c->d_K11, c->d_K12, c->d_F, c->d_Ua, c->d_Qa, c->d_V, c->d_R, c->d_G, c->d_x, c->d_r, c->d_z,
+                  c->d_K11, c->d_K12, c->d_F, c->d_Fem, c->d_Ua, c->d_Qa, c->d_V, c->d_R, c->d_G, c->d_x, c->d_r, c->d_z,
                   c->d_tmp, c->d_Un, c->d_partial, c->d_h};
   for (void* p : ptrs)
     if (p) hipFree(p);
@@ -246,6 +246,7 @@ static ldg_status assemble(ldg_ctx c, const double* U, double alpha, double gamm
   // BF16 factors are computed in an FP32 workspace stored after them
   const size_t fbytes = fprec == LDG_BF16 ? 2 * (((nF + 127) / 128) * 128) + 4 * nF : elem_size(fprec) * nF;
   TRY(grow(c, &c->d_F, &c->capF, fbytes));
+  TRY(grow(c, &c->d_Fem, &c->capFem, elem_size(fprec) * nF));
   TRY(dev_alloc(c, &c->d_Ua, (size_t)c->ndof));
   TRY(dev_alloc(c, &c->d_Qa, (size_t)c->nq));
   HIPCK(c, hipMemcpyAsync(c->d_Ua, U, sizeof(double) * c->ndof, hipMemcpyDeviceToDevice, dc.stream));
@@ -257,6 +258,7 @@ static ldg_status assemble(ldg_ctx c, const double* U, double alpha, double gamm
   c->learned_kept = keep;
   c->learned_active = false;
   HIPCK(c, launch_precond_factor(dc, c->d_K11, c->d_K12, prec, alpha, gamma, c->d_F, fprec, keep ? c->d_At : nullptr));
+  HIPCK(c, launch_precond_relayout(dc, c->d_F, fprec, c->d_Fem));
   c->assembled = true;
   c->prec = prec;
   c->alpha = alpha;

@@ -43,7 +43,9 @@ hipError_t launch_jacvec(const DevCtx& c, const void* K11, const void* K12, int 
 // K21 weights, then factorised by block ILU(0); factors [slot][c][c'][E*Np].
 hipError_t launch_precond_factor(const DevCtx& c, const void* K11, const void* K12, int prec, double alpha,
                                  double gamma, void* F, int fprec, float* At_copy = nullptr);
-hipError_t launch_precond_apply(const DevCtx& c, const void* F, int fprec, const double* r, double* z);
+// Element-major copy [E Np][slot][c][c'] of the factors, read by the apply.
+hipError_t launch_precond_relayout(const DevCtx& c, const void* F, int fprec, void* Fem);
+hipError_t launch_precond_apply(const DevCtx& c, const void* Fem, int fprec, const double* r, double* z);
 
 // Conversions of the internal layouts to the FP64 exchange layouts of ldg.h.
 hipError_t launch_export_blocks(const DevCtx& c, const void* K, int prec, int nslot, int ncol, double* out);

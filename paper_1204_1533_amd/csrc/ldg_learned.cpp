@@ -189,10 +189,10 @@ ldg_status learned_after_form(ldg_ctx c, const double* R_at_U, double gamma) {
 ldg_status precond_apply_any(ldg_ctx c, const double* r, double* z) {
   const DevCtx& dc = c->dc;
   if (!c->learned_active) {
-    HIPCK(c, launch_precond_apply(dc, c->d_F, c->prec, r, z));
+    HIPCK(c, launch_precond_apply(dc, c->d_Fem, c->prec, r, z));
     return LDG_OK;
   }
-  HIPCK(c, launch_precond_apply(dc, c->d_F, c->prec, r, c->d_z0));
+  HIPCK(c, launch_precond_apply(dc, c->d_Fem, c->prec, r, c->d_z0));
   HIPCK(c, launch_learned_apply(dc, c->d_At, c->d_C, r, c->d_z0, z));
   return LDG_OK;
 }
@@ -387,7 +387,7 @@ ldg_status ldg_learned_samples(ldg_ctx c, const int64_t* elems, int64_t n, const
   ldg_status st = LDG_OK;
   hipError_t e = hipMemcpyAsync(d_el, elems, sizeof(int64_t) * n, hipMemcpyHostToDevice, dc.stream);
   for (int k = 0; k < K && e == hipSuccess; ++k)
-    e = launch_precond_apply(dc, c->d_F, c->prec, V + (int64_t)k * nd, Z0 + (int64_t)k * nd);
+    e = launch_precond_apply(dc, c->d_Fem, c->prec, V + (int64_t)k * nd, Z0 + (int64_t)k * nd);
   if (e == hipSuccess)
     e = launch_learned_samples(dc, d_el, n, K, c->d_At, c->d_Xf, c->d_Dinv, V, Z0, nd, X, A, S, T);
   if (e == hipSuccess) e = hipStreamSynchronize(dc.stream);
