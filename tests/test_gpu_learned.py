@@ -294,3 +294,36 @@ def test_zero_output_and_nonfinite_fallback():
     ctx.close()
     ref_ctx.close()
     net.close()
+
+
+# ------------------------------------------------------------------ what the trained network gains
+def test_learned_gain_over_ilu0():
+    """Train on solver-generated samples (12^3, p = 3 Navier-Stokes runs, seeds 0-7), then compare
+    one BDF2 Newton step with and without the correction on held-out seeds 1000-1003.
+
+    The gain has no oracle (the paper has no learned part): the Newton residual judges the
+    error, so both solves must reach the 1e-8 linear tolerance and give the same Newton
+    residual, and the corrected preconditioner must need fewer GMRES iterations in total.
+    """
+    from paper_1204_1533_amd import learned
+    print("[gpu] learned gain 12^3", flush=True)
+    data = learned.generate(list(range(8)), n=12, steps=4, n_elem=256, n_probe=4, log=False)
+    net = Net(3, 3, 5, hidden=256, seed=1, stream=stream())
+    hist = learned.train(net, data, iters=1500, batch=256, lr=1e-3, log=False)
+    first, last = hist[0], float(np.mean(hist[-100:]))
+    print(f"  training loss {first:.4f} -> {last:.4f}", flush=True)
+    assert last < 0.2 * first
+    rows = learned.evaluate(net, [1000, 1001, 1002, 1003], n=12, log=False)
+    tot = {"ilu0": 0, "learned": 0}
+    for r in rows:
+        a, b = r["ilu0"], r["learned"]
+        print(f"  seed {r['seed']} (Re {r['re']:.0f}, M {r['mach']:.2f}): GMRES {a['gmres_iters']} -> "
+              f"{b['gmres_iters']}, ||G|| after {a['newton_res_after']:.6e} / {b['newton_res_after']:.6e}", flush=True)
+        assert a["lin_relres"] <= 1e-8 and b["lin_relres"] <= 1e-8
+        assert b["fallback_used"] == 0
+        assert abs(a["newton_res_after"] - b["newton_res_after"]) <= 1e-6 * a["newton_res_after"]
+        tot["ilu0"] += a["gmres_iters"]
+        tot["learned"] += b["gmres_iters"]
+    print(f"  total GMRES iterations: ILU(0) {tot['ilu0']}, learned {tot['learned']}", flush=True)
+    assert tot["learned"] < tot["ilu0"]
+    net.close()
