@@ -39,6 +39,29 @@ def parse():
 
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "jacvec_tgv32p4_bf16_traffic.md")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the split product from the committed rocprofv3 counter summary.
+
+    The summary records FETCH_SIZE / WRITE_SIZE per dispatch scaled by the same counters on a
+    plain conversion kernel of known size, and the SHA-256 of the kernel source it was taken
+    with; a changed source makes the figure stale, and then None is reported.
+    """
+    import hashlib
+    import re
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    txt = open(TRAFFIC_FILE).read()
+    m_b = re.search(r"jacvec_traffic_bytes_per_launch\s*=\s*([0-9.eE+]+)", txt)
+    m_h = re.search(r"source_sha256\s*=\s*([0-9a-f]{64})", txt)
+    if not m_b or not m_h:
+        return None
+    src = os.path.join(ROOT, "paper_1204_1533_amd", "csrc", "k_precond.hip")
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != m_h.group(1):
+        return None
+    return float(m_b.group(1))
 
 
 def roofline(pr, reps, prec):
@@ -74,6 +97,8 @@ def roofline(pr, reps, prec):
                    "traffic": None, "avg_ms": avg_ms, "launches": n, "bytes_per_launch": byts,
                    "share_of_step_ms": tot / len(reps)}
     dom = max(allk, key=lambda k: allk[k]["share_of_step_ms"]) if allk else None
+    if "jacvec" in allk and prec == 2 and me.n_elem == 32768 and p == 4:
+        allk["jacvec"]["traffic"] = measured_traffic()
     d = dict(allk[dom]) if dom else None
     if d:
         d["kernel"] = dom

@@ -38,7 +38,10 @@ struct JacLayout {
   static constexpr int oA = oJ + NP;
   static constexpr int oFi = oA + NL * NG * M * M;
   static constexpr int oFo = oFi + NL * 2 * M * M;
-  static constexpr int ndoubles = oFo + NL * 2 * M * M;
+  static constexpr int oOps = oFo + NL * 2 * M * M;  // copy of the 1-D operators
+  static constexpr int oDiag = oOps + (int)(sizeof(LineOps) / sizeof(double));
+  static constexpr int NITEM_ = (NP * M * M + NT_ELEM - 1) / NT_ELEM;
+  static constexpr int ndoubles = oDiag + NITEM_ * NT_ELEM;  // per-thread self-slot sums
   static constexpr size_t bytes = sizeof(double) * ndoubles;
   static constexpr int NITEM = (NP * M * M + NT_ELEM - 1) / NT_ELEM;
   static constexpr int NS11 = D * P + 1 + 2 * D;
@@ -52,14 +55,14 @@ __device__ __forceinline__ int line_slot(int n, int t, int tp) {
 }
 
 template <int D, int P, int EQ, int PR>
-__global__ void __launch_bounds__(NT_ELEM) jac_kernel(LineOps ops, MeshParams mp, const double* __restrict__ U,
+__global__ void __launch_bounds__(NT_ELEM) jac_kernel(LineOps ops_arg, MeshParams mp, const double* __restrict__ U,
                                                       const double* __restrict__ Q, void* __restrict__ K11,
                                                       void* __restrict__ K12) {
   using L = JacLayout<D, P, EQ>;
   constexpr int N1 = L::N1, NG = L::NG, NP = L::NP, NL = L::NL, M = L::M, QW = L::QW;
   constexpr bool INV = Eq<D, EQ>::INV, VIS = Eq<D, EQ>::VIS;
   constexpr int NSL = D * P + 1;
-  typedef Dual<M> T;
+  typedef Dual<1> T1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* sm = reinterpret_cast<double*>(smem_raw);
   double* sU = sm + L::oU;
@@ -78,6 +81,13 @@ __global__ void __launch_bounds__(NT_ELEM) jac_kernel(LineOps ops, MeshParams mp
   if constexpr (VIS)
     for (int i = tid; i < QW * NP; i += NT_ELEM) sQ[i] = Q[e * QW * NP + i];
   for (int i = tid; i < D * NP; i += NT_ELEM) sX[i] = mp.xyz[e * D * NP + i];
+  // the 1-D operators are indexed by per-lane positions; from LDS that is a
+  // plain load, from the kernel argument it would need private copies
+  {
+    const double* src = reinterpret_cast<const double*>(&ops_arg);
+    for (int i = tid; i < (int)(sizeof(LineOps) / sizeof(double)); i += NT_ELEM) sm[L::oOps + i] = src[i];
+  }
+  const LineOps& ops = *reinterpret_cast<const LineOps*>(sm + L::oOps);
   __syncthreads();
   for (int i = tid; i < D * D * NP; i += NT_ELEM) {
     const int ab = i / NP, node = i % NP;
@@ -103,9 +113,11 @@ __global__ void __launch_bounds__(NT_ELEM) jac_kernel(LineOps ops, MeshParams mp
 
   constexpr int NPART = VIS ? 1 + D : 1;
   for (int part = 0; part < NPART; ++part) {
-    double diag[L::NITEM];
+    // self-slot sums over the D directions, one LDS entry per (item, thread):
+    // kept out of registers, which the flux evaluations need
+    double* diag = sm + L::oDiag;
 #pragma unroll
-    for (int q = 0; q < L::NITEM; ++q) diag[q] = 0.0;
+    for (int q = 0; q < L::NITEM; ++q) diag[q * NT_ELEM + tid] = 0.0;
     const int dq = part - 1;  // derivative direction of q for part > 0
     for (int n = 0; n < D; ++n) {
       // ---- volume flux Jacobians at the Gauss points of every direction-n line
@@ -127,43 +139,69 @@ __global__ void __launch_bounds__(NT_ELEM) jac_kernel(LineOps ops, MeshParams mp
             G[a][b] = acc;
           }
         cofactor_row<D>(G, n, an);
-        T u[M], f[M];
-#pragma unroll
-        for (int c = 0; c < M; ++c) {
-          double acc = 0.0;
-#pragma unroll
-          for (int t = 0; t < N1; ++t) acc += ops.I[g][t] * sU[c * NP + line_node<D, N1>(n, l, t)];
-          u[c] = mk<M>(acc);
-          if (part == 0) u[c].d[c] = 1.0;
-          f[c] = mk<M>(0.0);
-        }
+        double qd[VIS ? M * D : 1];
         if constexpr (VIS) {
-          T q[M * D];
 #pragma unroll
           for (int k = 0; k < M * D; ++k) {
             double acc = 0.0;
 #pragma unroll
             for (int t = 0; t < N1; ++t) acc += ops.I[g][t] * sQ[k * NP + line_node<D, N1>(n, l, t)];
-            q[k] = mk<M>(acc);
-          }
-          if (part > 0) {
-#pragma unroll
-            for (int c = 0; c < M; ++c) q[c * D + dq].d[c] = 1.0;
-          }
-          visc_flux_dot_add<D, EQ, T>(u, q, an, mp.gamma, mp.mu, mp.prandtl, f);
-        }
-        if constexpr (INV) {
-          if (part == 0) {
-            T fi[M];
-            euler_flux_dot<D, T>(u, an, mp.gamma, fi);
-#pragma unroll
-            for (int c = 0; c < M; ++c) f[c] += fi[c];
+            qd[k] = acc;
           }
         }
+        if (part == 0) {
+          // d f / d u, one state component per pass (single-tangent duals);
+          // the gradient is a constant here
+          double ud[M];
 #pragma unroll
-        for (int c = 0; c < M; ++c)
+          for (int c = 0; c < M; ++c) {
+            double acc = 0.0;
 #pragma unroll
-          for (int k = 0; k < M; ++k) sA[((l * NG + g) * M + c) * M + k] = f[c].d[k];
+            for (int t = 0; t < N1; ++t) acc += ops.I[g][t] * sU[c * NP + line_node<D, N1>(n, l, t)];
+            ud[c] = acc;
+          }
+#pragma unroll 1
+          for (int k = 0; k < M; ++k) {
+            T1 u[M], f[M];
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+              u[c] = mk<1>(ud[c]);
+              u[c].d[0] = c == k ? 1.0 : 0.0;
+              f[c] = mk<1>(0.0);
+            }
+            if constexpr (VIS) visc_flux_dot_add<D, EQ, T1, double>(u, qd, an, mp.gamma, mp.mu, mp.prandtl, f);
+            if constexpr (INV) {
+              T1 fi[M];
+              euler_flux_dot<D, T1>(u, an, mp.gamma, fi);
+#pragma unroll
+              for (int c = 0; c < M; ++c) f[c] += fi[c];
+            }
+#pragma unroll
+            for (int c = 0; c < M; ++c) sA[((l * NG + g) * M + c) * M + k] = f[c].d[0];
+          }
+        } else if constexpr (VIS) {
+          // d f / d q_{:,dq}: F^vis is linear in q with no q-free term, so
+          // column k is F^vis(u, e_{k,dq}); the inviscid flux has no q
+          double ud[M];
+#pragma unroll
+          for (int c = 0; c < M; ++c) {
+            double acc = 0.0;
+#pragma unroll
+            for (int t = 0; t < N1; ++t) acc += ops.I[g][t] * sU[c * NP + line_node<D, N1>(n, l, t)];
+            ud[c] = acc;
+          }
+#pragma unroll 1
+          for (int k = 0; k < M; ++k) {
+            double ek[M * D], fk[M];
+#pragma unroll
+            for (int j = 0; j < M * D; ++j) ek[j] = (j == k * D + dq) ? 1.0 : 0.0;
+#pragma unroll
+            for (int c = 0; c < M; ++c) fk[c] = 0.0;
+            visc_flux_dot_add<D, EQ, double>(ud, ek, an, mp.gamma, mp.mu, mp.prandtl, fk);
+#pragma unroll
+            for (int c = 0; c < M; ++c) sA[((l * NG + g) * M + c) * M + k] = fk[c];
+          }
+        }
       }
       // ---- face flux Jacobians at both ends of every direction-n line
       for (int it = tid; it < NL * 2; it += NT_ELEM) {
@@ -202,6 +240,7 @@ __global__ void __launch_bounds__(NT_ELEM) jac_kernel(LineOps ops, MeshParams mp
           }
         }
         // derivative with respect to the inside (side 0) and outside (side 1) variable
+        const bool use_out = !bnd && S > 0;  // the side whose viscous flux the switch selects
         for (int side = 0; side < 2; ++side) {
           double* dst = (side == 0 ? sFi : sFo) + ((l * 2 + s) * M) * M;
           if (side == 1 && bnd) {
@@ -209,45 +248,53 @@ __global__ void __launch_bounds__(NT_ELEM) jac_kernel(LineOps ops, MeshParams mp
             for (int k = 0; k < M * M; ++k) dst[k] = 0.0;
             continue;
           }
-          T ti[M], to[M], F[M];
+          if (part == 0) {
+            double qs[VIS ? M * D : 1];
 #pragma unroll
-          for (int c = 0; c < M; ++c) {
-            ti[c] = mk<M>(uin[c]);
-            to[c] = mk<M>(uout[c]);
-            if (part == 0) {
-              if (side == 0) ti[c].d[c] = 1.0;
-              else to[c].d[c] = 1.0;
-            }
-          }
-          if constexpr (VIS) {
-            T tqi[M * D], tqo[M * D];
-#pragma unroll
-            for (int k = 0; k < M * D; ++k) {
-              tqi[k] = mk<M>(qin[k]);
-              tqo[k] = mk<M>(qout[k]);
-            }
-            if (part > 0) {
+            for (int k = 0; k < (VIS ? M * D : 1); ++k) qs[k] = VIS ? (use_out ? qout[k] : qin[k]) : 0.0;
+            // one state component of this side per pass
+#pragma unroll 1
+            for (int k = 0; k < M; ++k) {
+              T1 ti[M], to[M], F[M];
 #pragma unroll
               for (int c = 0; c < M; ++c) {
-                if (side == 0) tqi[c * D + dq].d[c] = 1.0;
-                else tqo[c * D + dq].d[c] = 1.0;
+                ti[c] = mk<1>(uin[c]);
+                to[c] = mk<1>(uout[c]);
+                const double seed = c == k ? 1.0 : 0.0;
+                ti[c].d[0] = side == 0 ? seed : 0.0;
+                to[c].d[0] = side == 0 ? 0.0 : seed;
               }
-              face_flux_point_io<D, EQ, T, false>(ti, tqi, to, tqo, nrm, S, bnd, mp, F);
-            } else {
-              face_flux_point_io<D, EQ, T, true>(ti, tqi, to, tqo, nrm, S, bnd, mp, F);
+              face_flux_point<D, EQ, T1, true, double>(ti, to, qs, nrm, S, bnd, mp, F);
+#pragma unroll
+              for (int c = 0; c < M; ++c) dst[c * M + k] = F[c].d[0];
             }
-          } else {
-            face_flux_point_io<D, EQ, T, true>(ti, ti, to, to, nrm, S, bnd, mp, F);
+          } else if constexpr (VIS) {
+            // only the selected side's gradient enters the flux, linearly
+            if ((side == 1) != use_out) {
+#pragma unroll
+              for (int k = 0; k < M * M; ++k) dst[k] = 0.0;
+              continue;
+            }
+            double us[M];
+#pragma unroll
+            for (int c = 0; c < M; ++c) us[c] = use_out ? uout[c] : uin[c];
+#pragma unroll 1
+            for (int k = 0; k < M; ++k) {
+              double ek[M * D], fk[M];
+#pragma unroll
+              for (int j = 0; j < M * D; ++j) ek[j] = (j == k * D + dq) ? 1.0 : 0.0;
+#pragma unroll
+              for (int c = 0; c < M; ++c) fk[c] = 0.0;
+              visc_flux_dot_add<D, EQ, double>(us, ek, nrm, mp.gamma, mp.mu, mp.prandtl, fk);
+#pragma unroll
+              for (int c = 0; c < M; ++c) dst[c * M + k] = fk[c];
+            }
           }
-#pragma unroll
-          for (int c = 0; c < M; ++c)
-#pragma unroll
-            for (int k = 0; k < M; ++k) dst[c * M + k] = F[c].d[k];
         }
       }
       __syncthreads();
       // ---- contraction into the block rows
-#pragma unroll
+#pragma unroll 1
       for (int q = 0; q < L::NITEM; ++q) {
         const int item = tid + q * NT_ELEM;
         if (item < NP * M * M) {
@@ -267,7 +314,7 @@ __global__ void __launch_bounds__(NT_ELEM) jac_kernel(LineOps ops, MeshParams mp
             if (tp == 0) v += ops.L0[t] * sFi[((l * 2 + 0) * M + c) * M + k];
             v *= sc;
             if (tp == t) {
-              diag[q] += v;
+              diag[q * NT_ELEM + tid] += v;
             } else {
               const int slot = line_slot<D, N1>(n, t, tp);
               if (part == 0)
@@ -299,9 +346,9 @@ __global__ void __launch_bounds__(NT_ELEM) jac_kernel(LineOps ops, MeshParams mp
         const int slot = a % N1;
         const int64_t gn = e * NP + a;
         if (part == 0)
-          Store<PR>::put(K11, ((int64_t)(slot * M + c) * M + k) * NN + gn, diag[q]);
+          Store<PR>::put(K11, ((int64_t)(slot * M + c) * M + k) * NN + gn, diag[q * NT_ELEM + tid]);
         else
-          Store<PR>::put(K12, ((int64_t)(slot * M + c) * (M * D) + k * D + dq) * NN + gn, diag[q]);
+          Store<PR>::put(K12, ((int64_t)(slot * M + c) * (M * D) + k * D + dq) * NN + gn, diag[q * NT_ELEM + tid]);
       }
     }
   }

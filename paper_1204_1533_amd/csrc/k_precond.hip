@@ -4,7 +4,8 @@
 // jacvec:   y = alpha x - gamma (K11 x + K12 w), w = K21 x computed by the
 //           gradient kernel with zero boundary data (eq. matvecsplit).  One
 //           thread per node streams its block row (node-fastest layout, so a
-//           wavefront reads contiguous memory for every (slot, c, c')).
+//           wavefront reads contiguous memory for every (slot, c, c')); the
+//           workgroup holds whole elements and stages their x and w in LDS.
 // form:     A~ = alpha I - gamma (K11 + K12 K21) restricted to the D lines
 //           through each node, K21 taken inside the element.  The K21 weights
 //           of a direction-n line are the scalar line operator
@@ -29,6 +30,12 @@
 namespace ldg {
 
 // --------------------------------------------------------------------------- jacvec
+// Elements per 256-thread workgroup of the product (one node per thread).
+template <int NP>
+__host__ __device__ constexpr int jv_epb() {
+  return NP >= 256 ? 1 : 256 / NP;
+}
+
 template <int D, int P, int EQ, int PR>
 __global__ void __launch_bounds__(256) jacvec_kernel(MeshParams mp, const void* __restrict__ K11,
                                                      const void* __restrict__ K12, double alpha, double gamma,
@@ -37,11 +44,24 @@ __global__ void __launch_bounds__(256) jacvec_kernel(MeshParams mp, const void* 
   constexpr int N1 = P + 1, NP = ipow(N1, D), NL = ipow(N1, D - 1), M = Eq<D, EQ>::M;
   constexpr bool VIS = Eq<D, EQ>::VIS;
   constexpr int NSL = D * P + 1, NS11 = NSL + 2 * D, NS12 = NSL + D, MD = M * D;
+  constexpr int EPB = jv_epb<NP>();
+  // The block's elements' x and w (contiguous in HBM) are staged in LDS: every
+  // node reads the x / w of its D lines many times, and those reads would
+  // otherwise miss in L2 behind the stream of Jacobian blocks.
+  __shared__ double sx[EPB * M * NP];
+  __shared__ double sw[VIS ? EPB * MD * NP : 1];
   const int64_t NN = mp.E * NP;
-  const int64_t gn = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (gn >= NN) return;
-  const int64_t e = gn / NP;
-  const int a = (int)(gn % NP);
+  const int64_t e0 = xcd_block(blockIdx.x, gridDim.x) * EPB;
+  const int nel = (int)(mp.E - e0 < EPB ? mp.E - e0 : EPB);
+  for (int i = threadIdx.x; i < nel * M * NP; i += 256) sx[i] = x[e0 * M * NP + i];
+  if constexpr (VIS)
+    for (int i = threadIdx.x; i < nel * MD * NP; i += 256) sw[i] = w[e0 * MD * NP + i];
+  __syncthreads();
+  const int le = threadIdx.x / NP, a = threadIdx.x % NP;
+  if (le >= nel) return;  // no barrier below this point
+  const int64_t e = e0 + le;
+  const int64_t gn = e * NP + a;
+  const double* lx = sx + le * M * NP;
   double acc[M];
 #pragma unroll
   for (int c = 0; c < M; ++c) acc[c] = 0.0;
@@ -49,32 +69,37 @@ __global__ void __launch_bounds__(256) jacvec_kernel(MeshParams mp, const void* 
   // kernel spills and drops to one wavefront per SIMD
 #pragma unroll 1
   for (int s = 0; s < NS11; ++s) {
-    int64_t col;
+    double xv[M];
     if (s < NSL) {
-      col = e * NP + slot_col<D, P>(a, s);
+      const int b = slot_col<D, P>(a, s);
+#pragma unroll
+      for (int k = 0; k < M; ++k) xv[k] = lx[k * NP + b];
     } else {
       const int f = s - NSL, n = f / 2;
       const int64_t nb = mp.face_nbr[e * 2 * D + f];
       if (nb < 0) continue;
       int l, t;
       node_line<N1>(a, n, l, t);
-      col = nb * NP + mp.nbr_node[(e * 2 * D + f) * NL + l];
-    }
-    const int64_t ce = col / NP, ca = col % NP;
-    double xv[M];
+      const int ca = mp.nbr_node[(e * 2 * D + f) * NL + l];
 #pragma unroll
-    for (int k = 0; k < M; ++k) xv[k] = x[(ce * M + k) * NP + ca];
+      for (int k = 0; k < M; ++k) xv[k] = x[(nb * M + k) * NP + ca];
+    }
 #pragma unroll
     for (int c = 0; c < M; ++c)
 #pragma unroll
       for (int k = 0; k < M; ++k) acc[c] += Store<PR>::get(K11, ((int64_t)(s * M + c) * M + k) * NN + gn) * xv[k];
   }
   if constexpr (VIS) {
+    const double* lw = sw + le * MD * NP;
 #pragma unroll 1
     for (int s = 0; s < NS12; ++s) {
-      int64_t col;
+      const double* src;
+      int64_t stride_base;
+      int ca;
       if (s < NSL) {
-        col = e * NP + slot_col<D, P>(a, s);
+        src = lw;
+        stride_base = 0;
+        ca = slot_col<D, P>(a, s);
       } else {
         const int n = s - NSL;
         const int side = mp.sw[e * D + n] > 0 ? 1 : 0;
@@ -83,12 +108,13 @@ __global__ void __launch_bounds__(256) jacvec_kernel(MeshParams mp, const void* 
         if (nb < 0) continue;
         int l, t;
         node_line<N1>(a, n, l, t);
-        col = nb * NP + mp.nbr_node[(e * 2 * D + f) * NL + l];
+        src = w;
+        stride_base = nb * MD * NP;
+        ca = mp.nbr_node[(e * 2 * D + f) * NL + l];
       }
-      const int64_t ce = col / NP, ca = col % NP;
 #pragma unroll
       for (int k = 0; k < MD; ++k) {
-        const double wv = w[(ce * MD + k) * NP + ca];
+        const double wv = src[stride_base + k * NP + ca];
 #pragma unroll
         for (int c = 0; c < M; ++c) acc[c] += Store<PR>::get(K12, ((int64_t)(s * M + c) * MD + k) * NN + gn) * wv;
       }
@@ -97,15 +123,15 @@ __global__ void __launch_bounds__(256) jacvec_kernel(MeshParams mp, const void* 
 #pragma unroll
   for (int c = 0; c < M; ++c) {
     const int64_t i = (e * M + c) * NP + a;
-    y[i] = alpha * x[i] - gamma * acc[c];
+    y[i] = alpha * lx[c * NP + a] - gamma * acc[c];
   }
 }
 
 hipError_t launch_jacvec(const DevCtx& dc, const void* K11, const void* K12, int prec, double alpha, double gamma,
                          const double* x, const double* w, double* y) {
-  const int64_t NN = dc.E * dc.NP;
-  const unsigned grid = (unsigned)((NN + 255) / 256);
   LDG_DISPATCH(dc, {
+    constexpr int EPB = jv_epb<ipow(P + 1, D)>();
+    const unsigned grid = (unsigned)((dc.E + EPB - 1) / EPB);
     LDG_PREC_DISPATCH(prec, {
       hipLaunchKernelGGL((jacvec_kernel<D, P, EQ, PR>), dim3(grid), dim3(256), 0, dc.stream, dc.mp, K11, K12, alpha,
                          gamma, x, w, y);
@@ -428,7 +454,7 @@ template <int D, int P, int EQ, int FP>
 __global__ void __launch_bounds__(64) apply_kernel(int64_t E, const void* __restrict__ F, const double* __restrict__ r,
                                                    double* __restrict__ z) {
   constexpr int N1 = P + 1, NP = ipow(N1, D), M = Eq<D, EQ>::M;
-  constexpr int RPP = 64 / M, NSLMM = (D * P + 1) * M * M;
+  constexpr int NSL = D * P + 1, RPP = 64 / M, NSLMM = NSL * M * M;
   // F: element-major copy of the factors, [E Np][slot][c][c'] (one element's
   // factors are contiguous, so a workgroup reads whole cache lines)
   __shared__ int rows[NP];
@@ -453,15 +479,18 @@ __global__ void __launch_bounds__(64) apply_kernel(int64_t E, const void* __rest
         const int64_t gi = e * NP + i;
         const int self_i = i % N1;
         acc = sy[i * M + c];
-        for (int n = 0; n < D; ++n) {
-          int l, ti;
-          node_line<N1>(i, n, l, ti);
-          for (int tk = 0; tk < ti; ++tk) {
-            const int k = line_node<D, N1>(n, l, tk);
-            const int s = slot_of<N1>(n, ti, tk, self_i);
+        // all line slots with compile-time bounds; the strictly lower ones
+        // (column before i in natural order) count, so every load of the row
+        // can be in flight at once.  Slot order = direction-major, position-
+        // ascending, the order of the elimination.
 #pragma unroll
-            for (int q = 0; q < M; ++q) acc -= Store<FP>::get(F, gi * NSLMM + (s * M + c) * M + q) * sy[k * M + q];
-          }
+        for (int s = 0; s < NSL; ++s) {
+          const int k = slot_col<D, P>(i, s);
+          const double msk = k < i ? 1.0 : 0.0;
+          double t = 0.0;
+#pragma unroll
+          for (int q = 0; q < M; ++q) t += Store<FP>::get(F, gi * NSLMM + (s * M + c) * M + q) * sy[k * M + q];
+          acc -= msk * t;
         }
       }
       __syncthreads();
@@ -481,15 +510,14 @@ __global__ void __launch_bounds__(64) apply_kernel(int64_t E, const void* __rest
         const int64_t gi = e * NP + i;
         const int self_i = i % N1;
         double acc = sy[i * M + c];
-        for (int n = 0; n < D; ++n) {
-          int l, ti;
-          node_line<N1>(i, n, l, ti);
-          for (int tj = ti + 1; tj < N1; ++tj) {
-            const int j = line_node<D, N1>(n, l, tj);
-            const int s = slot_of<N1>(n, ti, tj, self_i);
 #pragma unroll
-            for (int q = 0; q < M; ++q) acc -= Store<FP>::get(F, gi * NSLMM + (s * M + c) * M + q) * sy[j * M + q];
-          }
+        for (int s = 0; s < NSL; ++s) {
+          const int j = slot_col<D, P>(i, s);
+          const double msk = j > i ? 1.0 : 0.0;
+          double t = 0.0;
+#pragma unroll
+          for (int q = 0; q < M; ++q) t += Store<FP>::get(F, gi * NSLMM + (s * M + c) * M + q) * sy[j * M + q];
+          acc -= msk * t;
         }
         st[i * M + c] = acc;
       }
@@ -514,14 +542,26 @@ __global__ void convert_kernel(const void* __restrict__ in, void* __restrict__ o
     Store<POUT>::put(out, i, Store<PIN>::get(in, i));
 }
 
-// node-fastest [q][E Np] -> element-major [E Np][q], q = (slot, c, c')
+// node-fastest [q][E Np] -> element-major [E Np][q], q = (slot, c, c'):
+// a 32 (q) x 64 (node) tile goes through LDS so that both the reads (along
+// nodes) and the writes (along q) are contiguous.
 template <int PR>
-__global__ void relayout_kernel(const void* __restrict__ in, void* __restrict__ out, int64_t NN, int nq) {
-  const int64_t n = NN * nq;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t gn = i / nq;
-    const int q = (int)(i % nq);
-    Store<PR>::put(out, i, Store<PR>::get(in, (int64_t)q * NN + gn));
+__global__ void __launch_bounds__(256) relayout_kernel(const void* __restrict__ in, void* __restrict__ out, int64_t NN,
+                                                       int nq) {
+  using T = typename Store<PR>::type;
+  __shared__ T tile[32][64 + 1];
+  const int64_t g0 = (int64_t)blockIdx.x * 64;
+  const int q0 = blockIdx.y * 32;
+  const T* src = (const T*)in;
+  T* dst = (T*)out;
+  for (int i = threadIdx.x; i < 32 * 64; i += 256) {
+    const int qq = i / 64, gg = i % 64;
+    if (q0 + qq < nq && g0 + gg < NN) tile[qq][gg] = src[(int64_t)(q0 + qq) * NN + g0 + gg];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 32 * 64; i += 256) {
+    const int gg = i / 32, qq = i % 32;
+    if (q0 + qq < nq && g0 + gg < NN) dst[(g0 + gg) * nq + q0 + qq] = tile[qq][gg];
   }
 }
 
@@ -578,7 +618,8 @@ hipError_t launch_precond_relayout(const DevCtx& dc, const void* F, int fprec, v
   const int64_t NN = dc.E * dc.NP;
   const int nq = (dc.D * dc.P + 1) * dc.M * dc.M;
   LDG_PREC_DISPATCH(fprec, {
-    hipLaunchKernelGGL((relayout_kernel<PR>), dim3(copy_grid(NN * nq)), dim3(256), 0, dc.stream, F, Fem, NN, nq);
+    const dim3 grid((unsigned)((NN + 63) / 64), (unsigned)((nq + 31) / 32));
+    hipLaunchKernelGGL((relayout_kernel<PR>), grid, dim3(256), 0, dc.stream, F, Fem, NN, nq);
     return hipGetLastError();
   })
 }

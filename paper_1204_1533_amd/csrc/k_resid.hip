@@ -125,7 +125,7 @@ __global__ void __launch_bounds__(NT_ELEM) resid_kernel(LineOps ops, MeshParams 
   double* sAg = reinterpret_cast<double*>(smem_raw + L::oA);
   constexpr int NW = L::NW;
 
-  const int64_t e0 = (int64_t)blockIdx.x * EPB;
+  const int64_t e0 = xcd_block(blockIdx.x, gridDim.x) * EPB;
   const int ne = (int)min((int64_t)EPB, mp.E - e0);
   const int tid = threadIdx.x;
 
@@ -310,7 +310,7 @@ __global__ void __launch_bounds__(NT_ELEM) grad_kernel(LineOps ops, MeshParams m
   double* sUh = sm + L::oUh;
   double* sNh = sm + L::oNh;
 
-  const int64_t e0 = (int64_t)blockIdx.x * EPB;
+  const int64_t e0 = xcd_block(blockIdx.x, gridDim.x) * EPB;
   const int ne = (int)min((int64_t)EPB, mp.E - e0);
   const int tid = threadIdx.x;
   for (int i = tid; i < ne * M * NP; i += NT_ELEM) sU[i] = U[e0 * M * NP + i];

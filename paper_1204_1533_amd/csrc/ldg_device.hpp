@@ -60,6 +60,17 @@ __device__ __forceinline__ void node_line(int node, int n, int& l, int& t) {
   l = (node % s) + (node / (s * N1)) * s;
 }
 
+// ---------------------------------------------------------------- XCD-aware block order
+// Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.  This
+// maps hardware block b of G to a logical block so that every XCD walks one
+// contiguous run of blocks (neighbouring elements then share an L2).  It is a
+// bijection on [0, G).
+constexpr int N_XCD = 8;
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t G) {
+  const int64_t x = b % N_XCD, k = b / N_XCD, per = G / N_XCD, rem = G % N_XCD;
+  return x * per + (x < rem ? x : rem) + k;
+}
+
 // ---------------------------------------------------------------- line-pattern slots
 // A row node a has D p + 1 line-pattern columns: slots 0..p are the nodes of its
 // direction-0 line by position (its own position is the diagonal slot); then,
