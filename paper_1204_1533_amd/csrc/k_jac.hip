@@ -13,11 +13,15 @@
 //
 // One workgroup per element.  For each part (u, then q_{:,d} for d < D) and
 // each direction, the m x m flux Jacobians at all Gauss points and line ends
-// are formed in LDS (one dual evaluation with m tangents per point); then one
-// thread per (row node, component pair) contracts them into every slot of its
-// block row.  The self slot sums the D directions in a register, so each
-// output is written exactly once, and consecutive threads write consecutive
-// nodes of the [slot][c][c'][node] layout.
+// are formed in LDS; then one thread per (row node, component pair) contracts
+// them into every slot of its block row.  The self slot sums the D directions
+// in LDS, so each output is written exactly once, and consecutive threads
+// write consecutive nodes of the [slot][c][c'][node] layout.
+// Flux Jacobians: d/du by m forward-mode passes with one tangent each (the
+// gradient held constant); d/dq exactly, since the viscous flux is linear in q
+// with no q-free part (column k of dF/dq_{:,d} is F^vis(u, e_{k,d})) and the
+// inviscid and penalty terms do not involve q.  The 1-D operators are copied
+// to LDS because every lane indexes them by its own line position.
 #include "ldg_dispatch.hpp"
 #include "ldg_kernels.hpp"
 #include "ldg_store.hpp"

@@ -376,10 +376,12 @@ template <int D, int P, int EQ, int WP>
 __global__ void __launch_bounds__(64) factor_kernel(int64_t E, void* __restrict__ F) {
   constexpr int N1 = P + 1, NP = ipow(N1, D), M = Eq<D, EQ>::M;
   constexpr int RPP = 64 / M;  // rows per pass
+  constexpr int NSLMM = (D * P + 1) * M * M;
+  // F: element-major [E Np][slot][c][c'], so one workgroup's rows are one
+  // contiguous block
   __shared__ int rows[NP];
   __shared__ int off[D * P + 2];
   const int64_t e = blockIdx.x;
-  const int64_t NN = E * NP;
   const int lane = threadIdx.x;
   if (lane == 0) level_table<D, P>(rows, off);
   __syncthreads();
@@ -403,17 +405,17 @@ __global__ void __launch_bounds__(64) factor_kernel(int64_t E, void* __restrict_
             // L_ik[c][:] = A_ik[c][:] Uinv_kk
             double arow[M], lrow[M];
 #pragma unroll
-            for (int q = 0; q < M; ++q) arow[q] = Store<WP>::get(F, ((int64_t)(sik * M + c) * M + q) * NN + gi);
+            for (int q = 0; q < M; ++q) arow[q] = Store<WP>::get(F, gi * NSLMM + (sik * M + c) * M + q);
             const int self_k = k % N1;
 #pragma unroll
             for (int j = 0; j < M; ++j) {
               double s = 0.0;
 #pragma unroll
-              for (int q = 0; q < M; ++q) s += arow[q] * Store<WP>::get(F, ((int64_t)(self_k * M + q) * M + j) * NN + gk);
+              for (int q = 0; q < M; ++q) s += arow[q] * Store<WP>::get(F, gk * NSLMM + (self_k * M + q) * M + j);
               lrow[j] = s;
             }
 #pragma unroll
-            for (int j = 0; j < M; ++j) Store<WP>::put(F, ((int64_t)(sik * M + c) * M + j) * NN + gi, lrow[j]);
+            for (int j = 0; j < M; ++j) Store<WP>::put(F, gi * NSLMM + (sik * M + c) * M + j, lrow[j]);
             // A_ij -= L_ik U_kj for j after k on the shared line
             for (int tj = tk + 1; tj < N1; ++tj) {
               const int sij = slot_of<N1>(n, ti, tj, self_i);
@@ -422,8 +424,8 @@ __global__ void __launch_bounds__(64) factor_kernel(int64_t E, void* __restrict_
               for (int j = 0; j < M; ++j) {
                 double s = 0.0;
 #pragma unroll
-                for (int q = 0; q < M; ++q) s += lrow[q] * Store<WP>::get(F, ((int64_t)(skj * M + q) * M + j) * NN + gk);
-                const int64_t idx = ((int64_t)(sij * M + c) * M + j) * NN + gi;
+                for (int q = 0; q < M; ++q) s += lrow[q] * Store<WP>::get(F, gk * NSLMM + (skj * M + q) * M + j);
+                const int64_t idx = gi * NSLMM + (sij * M + c) * M + j;
                 Store<WP>::put(F, idx, Store<WP>::get(F, idx) - s);
               }
             }
@@ -438,12 +440,12 @@ __global__ void __launch_bounds__(64) factor_kernel(int64_t E, void* __restrict_
 #pragma unroll
         for (int a = 0; a < M; ++a)
 #pragma unroll
-          for (int b = 0; b < M; ++b) A[a][b] = Store<WP>::get(F, ((int64_t)(self_i * M + a) * M + b) * NN + gi);
+          for (int b = 0; b < M; ++b) A[a][b] = Store<WP>::get(F, gi * NSLMM + (self_i * M + a) * M + b);
         invert_block<M>(A, Inv);
 #pragma unroll
         for (int a = 0; a < M; ++a)
 #pragma unroll
-          for (int b = 0; b < M; ++b) Store<WP>::put(F, ((int64_t)(self_i * M + a) * M + b) * NN + gi, Inv[a][b]);
+          for (int b = 0; b < M; ++b) Store<WP>::put(F, gi * NSLMM + (self_i * M + a) * M + b, Inv[a][b]);
       }
       __syncthreads();
     }
@@ -570,13 +572,17 @@ static unsigned copy_grid(int64_t n) {
   return (unsigned)(g > 65536 ? 65536 : g);
 }
 
-// At_copy (optional) receives A~ in FP32 before it is factorised.
-// F holds the factors in storage precision fprec.  For fprec = BF16 the
-// factorisation runs on an FP32 copy placed after the BF16 factors in F.
+// A~ is formed node-fastest in Fwork, copied (At_copy, optional) in FP32,
+// transposed to the element-major layout and factorised there in place; the
+// factors end in Fem in storage precision fprec.  Fwork holds nF entries of
+// the factorisation precision (FP64 for fprec = F64, FP32 otherwise) and, for
+// BF16, a second FP32 array of nF after them (the element-major work copy).
 hipError_t launch_precond_factor(const DevCtx& dc, const void* K11, const void* K12, int prec, double alpha,
-                                 double gamma, void* F, int fprec, float* At_copy) {
+                                 double gamma, void* Fwork, int fprec, void* Fem, float* At_copy) {
   const int64_t NN = dc.E * dc.NP;
-  const int64_t nF = NN * (int64_t)(dc.D * dc.P + 1) * dc.M * dc.M;
+  const int nq = (dc.D * dc.P + 1) * dc.M * dc.M;
+  const int64_t nF = NN * (int64_t)nq;
+  const dim3 tgrid((unsigned)((NN + 63) / 64), (unsigned)((nq + 31) / 32));
   LDG_DISPATCH(dc, {
     using L = FormLayout<D, P, EQ>;
     const size_t bytes = Eq<D, EQ>::VIS ? L::bytes : 0;
@@ -585,46 +591,43 @@ hipError_t launch_precond_factor(const DevCtx& dc, const void* K11, const void* 
         auto k = form_kernel<D, P, EQ, PR, PREC_F64>;
         if (bytes > 65536) hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         hipLaunchKernelGGL(k, dim3((unsigned)dc.E), dim3(NT_ELEM), bytes, dc.stream, dc.ops, dc.mp, K11, K12, alpha,
-                           gamma, F);
+                           gamma, Fwork);
         if (At_copy)
-          hipLaunchKernelGGL((convert_kernel<PREC_F64, PREC_F32>), dim3(copy_grid(nF)), dim3(256), 0, dc.stream, F,
+          hipLaunchKernelGGL((convert_kernel<PREC_F64, PREC_F32>), dim3(copy_grid(nF)), dim3(256), 0, dc.stream, Fwork,
                              At_copy, nF);
+        hipLaunchKernelGGL((relayout_kernel<PREC_F64>), tgrid, dim3(256), 0, dc.stream, Fwork, Fem, NN, nq);
         hipLaunchKernelGGL((factor_kernel<D, P, EQ, PREC_F64>), dim3((unsigned)dc.E), dim3(64), 0, dc.stream, dc.E,
-                           F);
+                           Fem);
       } else {
-        void* work = fprec == PREC_F32 ? F : (void*)((uint16_t*)F + ((nF + 127) / 128) * 128);
+        void* em = fprec == PREC_F32 ? Fem : (void*)((float*)Fwork + nF);
         auto k = form_kernel<D, P, EQ, PR, PREC_F32>;
         if (bytes > 65536) hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         hipLaunchKernelGGL(k, dim3((unsigned)dc.E), dim3(NT_ELEM), bytes, dc.stream, dc.ops, dc.mp, K11, K12, alpha,
-                           gamma, work);
+                           gamma, Fwork);
         if (At_copy)
-          hipLaunchKernelGGL((convert_kernel<PREC_F32, PREC_F32>), dim3(copy_grid(nF)), dim3(256), 0, dc.stream, work,
+          hipLaunchKernelGGL((convert_kernel<PREC_F32, PREC_F32>), dim3(copy_grid(nF)), dim3(256), 0, dc.stream, Fwork,
                              At_copy, nF);
-        hipLaunchKernelGGL((factor_kernel<D, P, EQ, PREC_F32>), dim3((unsigned)dc.E), dim3(64), 0, dc.stream, dc.E,
-                           work);
-        if (fprec == PREC_BF16) {
-          int64_t g = (nF + 255) / 256;
-          if (g > 65536) g = 65536;
-          hipLaunchKernelGGL((convert_kernel<PREC_F32, PREC_BF16>), dim3((unsigned)g), dim3(256), 0, dc.stream, work, F,
-                             nF);
-        }
+        hipLaunchKernelGGL((relayout_kernel<PREC_F32>), tgrid, dim3(256), 0, dc.stream, Fwork, em, NN, nq);
+        hipLaunchKernelGGL((factor_kernel<D, P, EQ, PREC_F32>), dim3((unsigned)dc.E), dim3(64), 0, dc.stream, dc.E, em);
+        if (fprec == PREC_BF16)
+          hipLaunchKernelGGL((convert_kernel<PREC_F32, PREC_BF16>), dim3(copy_grid(nF)), dim3(256), 0, dc.stream, em,
+                             Fem, nF);
       }
       return hipGetLastError();
     })
   })
 }
 
-hipError_t launch_precond_relayout(const DevCtx& dc, const void* F, int fprec, void* Fem) {
-  const int64_t NN = dc.E * dc.NP;
-  const int nq = (dc.D * dc.P + 1) * dc.M * dc.M;
+// element-major factors -> FP64 [E][Np][slot][c][c'] (the same order)
+hipError_t launch_factors_to_f64(const DevCtx& dc, const void* Fem, int fprec, double* out) {
+  const int64_t n = dc.E * dc.NP * (int64_t)((dc.D * dc.P + 1) * dc.M * dc.M);
   LDG_PREC_DISPATCH(fprec, {
-    const dim3 grid((unsigned)((NN + 63) / 64), (unsigned)((nq + 31) / 32));
-    hipLaunchKernelGGL((relayout_kernel<PR>), grid, dim3(256), 0, dc.stream, F, Fem, NN, nq);
+    hipLaunchKernelGGL((convert_kernel<PR, PREC_F64>), dim3(copy_grid(n)), dim3(256), 0, dc.stream, Fem, out, n);
     return hipGetLastError();
   })
 }
 
-// Fem: the element-major copy written by launch_precond_relayout.
+// Fem: the element-major factors written by launch_precond_factor.
 hipError_t launch_precond_apply(const DevCtx& dc, const void* F, int fprec, const double* r, double* z) {
   LDG_DISPATCH(dc, {
     LDG_PREC_DISPATCH(fprec, {

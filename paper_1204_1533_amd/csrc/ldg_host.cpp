@@ -243,8 +243,9 @@ static ldg_status assemble(ldg_ctx c, const double* U, double alpha, double gamm
   TRY(grow(c, &c->d_K12, &c->capK12, es * (size_t)ns12 * dc.M * dc.M * dc.D * c->nnode));
   const int fprec = prec;
   const size_t nF = (size_t)nsF * dc.M * dc.M * c->nnode;
-  // BF16 factors are computed in an FP32 workspace stored after them
-  const size_t fbytes = fprec == LDG_BF16 ? 2 * (((nF + 127) / 128) * 128) + 4 * nF : elem_size(fprec) * nF;
+  // A~ is formed node-fastest in d_F (FP64 for FP64 storage, FP32 otherwise;
+  // for BF16 an element-major FP32 copy follows it) and factorised into d_Fem
+  const size_t fbytes = fprec == LDG_F64 ? 8 * nF : (fprec == LDG_F32 ? 4 * nF : 8 * nF);
   TRY(grow(c, &c->d_F, &c->capF, fbytes));
   TRY(grow(c, &c->d_Fem, &c->capFem, elem_size(fprec) * nF));
   TRY(dev_alloc(c, &c->d_Ua, (size_t)c->ndof));
@@ -257,8 +258,8 @@ static ldg_status assemble(ldg_ctx c, const double* U, double alpha, double gamm
   if (keep) TRY(dev_alloc(c, &c->d_At, nF));
   c->learned_kept = keep;
   c->learned_active = false;
-  HIPCK(c, launch_precond_factor(dc, c->d_K11, c->d_K12, prec, alpha, gamma, c->d_F, fprec, keep ? c->d_At : nullptr));
-  HIPCK(c, launch_precond_relayout(dc, c->d_F, fprec, c->d_Fem));
+  HIPCK(c, launch_precond_factor(dc, c->d_K11, c->d_K12, prec, alpha, gamma, c->d_F, fprec, c->d_Fem,
+                                 keep ? c->d_At : nullptr));
   c->assembled = true;
   c->prec = prec;
   c->alpha = alpha;
@@ -310,10 +311,10 @@ ldg_status ldg_export_operators(ldg_ctx c, double* K11, double* K12, double* F) 
   if (!c) return LDG_E_INVALID;
   if (!c->assembled) return fail(c, LDG_E_NOT_ASSEMBLED, "call ldg_jacobian_assemble first");
   const DevCtx& dc = c->dc;
-  const int ns11 = dc.D * dc.P + 1 + 2 * dc.D, ns12 = dc.D * dc.P + 1 + dc.D, nsF = dc.D * dc.P + 1;
+  const int ns11 = dc.D * dc.P + 1 + 2 * dc.D, ns12 = dc.D * dc.P + 1 + dc.D;
   if (K11) HIPCK(c, launch_export_blocks(dc, c->d_K11, c->prec, ns11, dc.M, K11));
   if (K12) HIPCK(c, launch_export_blocks(dc, c->d_K12, c->prec, ns12, dc.M * dc.D, K12));
-  if (F) HIPCK(c, launch_export_blocks(dc, c->d_F, c->prec, nsF, dc.M, F));
+  if (F) HIPCK(c, launch_factors_to_f64(dc, c->d_Fem, c->prec, F));
   return LDG_OK;
 }
 

@@ -40,11 +40,11 @@ hipError_t launch_jacvec(const DevCtx& c, const void* K11, const void* K12, int 
                          const double* x, const double* w, double* y);
 
 // Preconditioner A~ (line pattern) formed from the stored K11/K12 and the
-// K21 weights, then factorised by block ILU(0); factors [slot][c][c'][E*Np].
+// K21 weights (node-fastest in Fwork), then factorised by block ILU(0) in the
+// element-major layout [E Np][slot][c][c']: factors in Fem (precision fprec).
 hipError_t launch_precond_factor(const DevCtx& c, const void* K11, const void* K12, int prec, double alpha,
-                                 double gamma, void* F, int fprec, float* At_copy = nullptr);
-// Element-major copy [E Np][slot][c][c'] of the factors, read by the apply.
-hipError_t launch_precond_relayout(const DevCtx& c, const void* F, int fprec, void* Fem);
+                                 double gamma, void* Fwork, int fprec, void* Fem, float* At_copy);
+hipError_t launch_factors_to_f64(const DevCtx& c, const void* Fem, int fprec, double* out);
 hipError_t launch_precond_apply(const DevCtx& c, const void* Fem, int fprec, const double* r, double* z);
 
 // Conversions of the internal layouts to the FP64 exchange layouts of ldg.h.
