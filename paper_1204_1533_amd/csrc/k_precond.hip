@@ -346,14 +346,18 @@ __device__ __forceinline__ void invert_block(double A[M][M], double Inv[M][M]) {
         best = fabs(W[r][c]);
         piv = r;
       }
-    if (piv != c) {
+    // row swap with compile-time row indices (a runtime row index would put
+    // W in scratch memory)
 #pragma unroll
-      for (int j = 0; j < 2 * M; ++j) {
-        double t = W[c][j];
-        W[c][j] = W[piv][j];
-        W[piv][j] = t;
+    for (int r = c + 1; r < M; ++r)
+      if (r == piv) {
+#pragma unroll
+        for (int j = 0; j < 2 * M; ++j) {
+          double t = W[c][j];
+          W[c][j] = W[r][j];
+          W[r][j] = t;
+        }
       }
-    }
     const double id = 1.0 / W[c][c];
 #pragma unroll
     for (int j = 0; j < 2 * M; ++j) W[c][j] *= id;
