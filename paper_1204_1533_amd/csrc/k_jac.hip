@@ -58,7 +58,10 @@ __device__ __forceinline__ int line_slot(int n, int t, int tp) {
   return n == 0 ? tp : N1 + (n - 1) * (N1 - 1) + (tp < t ? tp : tp - 1);
 }
 
-template <int D, int P, int EQ, int PR>
+// Parts [PART0, PART1) of the derivative passes: launched as two kernels, the
+// state part (K11, with tangents) and the gradient parts (K12, plain doubles),
+// so that each gets its own register allocation.
+template <int D, int P, int EQ, int PR, int PART0, int PART1>
 __global__ void __launch_bounds__(NT_ELEM) jac_kernel(LineOps ops_arg, MeshParams mp, const double* __restrict__ U,
                                                       const double* __restrict__ Q, void* __restrict__ K11,
                                                       void* __restrict__ K12) {
@@ -116,7 +119,7 @@ __global__ void __launch_bounds__(NT_ELEM) jac_kernel(LineOps ops_arg, MeshParam
   __syncthreads();
 
   constexpr int NPART = VIS ? 1 + D : 1;
-  for (int part = 0; part < NPART; ++part) {
+  for (int part = PART0; part < (PART1 < NPART ? PART1 : NPART); ++part) {
     // self-slot sums over the D directions, one LDS entry per (item, thread):
     // kept out of registers, which the flux evaluations need
     double* diag = sm + L::oDiag;
@@ -362,14 +365,19 @@ hipError_t launch_jacobian(const DevCtx& dc, const double* U, const double* Q, v
   LDG_DISPATCH(dc, {
     using L = JacLayout<D, P, EQ>;
     LDG_PREC_DISPATCH(prec, {
-      auto kern = jac_kernel<D, P, EQ, PR>;
+      auto k11 = jac_kernel<D, P, EQ, PR, 0, 1>;
+      auto k12 = jac_kernel<D, P, EQ, PR, 1, 1 + D>;
       if (L::bytes > 65536) {
         hipError_t err =
-            hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L::bytes);
+            hipFuncSetAttribute((const void*)k11, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L::bytes);
+        if (err == hipSuccess)
+          err = hipFuncSetAttribute((const void*)k12, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L::bytes);
         if (err != hipSuccess) return err;
       }
-      hipLaunchKernelGGL(kern, dim3((unsigned)dc.E), dim3(NT_ELEM), L::bytes, dc.stream, dc.ops, dc.mp, U, Q, K11,
-                         K12);
+      hipLaunchKernelGGL(k11, dim3((unsigned)dc.E), dim3(NT_ELEM), L::bytes, dc.stream, dc.ops, dc.mp, U, Q, K11, K12);
+      if constexpr (Eq<D, EQ>::VIS)
+        hipLaunchKernelGGL(k12, dim3((unsigned)dc.E), dim3(NT_ELEM), L::bytes, dc.stream, dc.ops, dc.mp, U, Q, K11,
+                           K12);
       return hipGetLastError();
     })
   })
