@@ -23,6 +23,8 @@
 //           on the line they share.  The diagonal slot keeps the inverse of
 //           the U diagonal block.
 // apply:    forward / backward block substitution over the same levels.
+#include <type_traits>
+
 #include "ldg_dispatch.hpp"
 #include "ldg_kernels.hpp"
 #include "ldg_store.hpp"
@@ -264,45 +266,89 @@ __global__ void __launch_bounds__(NT_ELEM) form_kernel(LineOps ops, MeshParams m
     }
     __syncthreads();
   }
-  // A~ entries: one work item per (row node, slot, c, c')
-  for (int it = tid; it < NP * NSL * M * M; it += NT_ELEM) {
-    const int a = it % NP;
-    const int r = it / NP;
-    const int k = r % M, c = (r / M) % M, slot = r / (M * M);
+  // A~ rows: one work item per (row node a, row component c).  For each of the
+  // D lines through a, row c of K12 on the line's p+1 slots is loaded once and
+  // gives the p+1 output blocks on that line:
+  //   (K12 K21)_ab[c][k] = sum_{c' on the line, c' != b} K12_ac'[c][k,:] . W_n[t_c'][t_b][:] / J_c'
+  //                      + K12_ab[c][k,:] . S_b[:]        (S_b: self weight of b over its D lines)
+  // The self block (b = a) collects the c' != a terms of all D lines.
+  using KT = typename std::conditional<PR == PREC_F64, double, float>::type;
+#pragma unroll 1
+  for (int it = tid; it < NP * M; it += NT_ELEM) {
+    const int a = it % NP, c = it / NP;
+    const int self = a % N1;
     const int64_t gn = e * NP + a;
-    double v = Store<PR>::get(K11, ((int64_t)(slot * M + c) * M + k) * NN + gn);
-    if constexpr (VIS) {
-      const int self = a % N1;
-      const int b = slot_col<D, P>(a, slot);
-      // c = b: the weight of b on itself sums all D lines through b
-      double prod = 0.0;
+    double self_acc[M];
 #pragma unroll
-      for (int d = 0; d < D; ++d)
-        prod += Store<PR>::get(K12, ((int64_t)(slot * M + c) * MD + k * D + d) * NN + gn) * sS[b * D + d];
-      // c != b on the line shared by a and b (for b = a, on every line through a)
-#pragma unroll
-      for (int n = 0; n < D; ++n) {
-        int la, ta, lb, tb;
-        node_line<N1>(a, n, la, ta);
-        node_line<N1>(b, n, lb, tb);
-        if (la != lb) continue;  // b is not on a's direction-n line
+    for (int k = 0; k < M; ++k) self_acc[k] = 0.0;
+#pragma unroll 1
+    for (int n = 0; n < D; ++n) {
+      int la, ta;
+      node_line<N1>(a, n, la, ta);
+      KT kc[VIS ? N1 : 1][VIS ? MD : 1];
+      double jc[N1];
+      if constexpr (VIS) {
 #pragma unroll
         for (int tc = 0; tc < N1; ++tc) {
-          if (tc == tb) continue;
           const int sc = slot_of<N1>(n, ta, tc, self);
-          const int cn = line_node<D, N1>(n, la, tc);
-          const double jc = sJ[cn];
 #pragma unroll
-          for (int d = 0; d < D; ++d)
-            prod += Store<PR>::get(K12, ((int64_t)(sc * M + c) * MD + k * D + d) * NN + gn) *
-                    sW[(((n * NL + la) * N1 + tc) * N1 + tb) * D + d] * jc;
+          for (int q = 0; q < MD; ++q) kc[tc][q] = (KT)Store<PR>::get(K12, ((int64_t)(sc * M + c) * MD + q) * NN + gn);
+          jc[tc] = sJ[line_node<D, N1>(n, la, tc)];
         }
       }
-      v += prod;
+#pragma unroll
+      for (int tb = 0; tb < N1; ++tb) {
+        const int b = line_node<D, N1>(n, la, tb);
+        const bool is_self = tb == ta;
+        if (is_self && !VIS) continue;
+        double prod[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) prod[k] = 0.0;
+        if constexpr (VIS) {
+#pragma unroll
+          for (int tc = 0; tc < N1; ++tc) {
+            if (tc == tb) continue;
+            double w[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d) w[d] = sW[(((n * NL + la) * N1 + tc) * N1 + tb) * D + d] * jc[tc];
+#pragma unroll
+            for (int k = 0; k < M; ++k)
+#pragma unroll
+              for (int d = 0; d < D; ++d) prod[k] += (double)kc[tc][k * D + d] * w[d];
+          }
+        }
+        if (is_self) {
+#pragma unroll
+          for (int k = 0; k < M; ++k) self_acc[k] += prod[k];
+          continue;
+        }
+        if constexpr (VIS) {
+#pragma unroll
+          for (int k = 0; k < M; ++k)
+#pragma unroll
+            for (int d = 0; d < D; ++d) prod[k] += (double)kc[tb][k * D + d] * sS[b * D + d];
+        }
+        const int slot = slot_of<N1>(n, ta, tb, self);
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+          const double v = Store<PR>::get(K11, ((int64_t)(slot * M + c) * M + k) * NN + gn) + prod[k];
+          Store<WP>::put(F, ((int64_t)(slot * M + c) * M + k) * NN + gn, -gamma * v);
+        }
+      }
     }
-    v = -gamma * v;
-    if (slot == a % N1 && c == k) v += alpha;
-    Store<WP>::put(F, ((int64_t)(slot * M + c) * M + k) * NN + gn, v);
+    // self block: K11 + the c' != a terms of all lines + K12_aa . S_a
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      double v = Store<PR>::get(K11, ((int64_t)(self * M + c) * M + k) * NN + gn) + self_acc[k];
+      if constexpr (VIS) {
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+          v += Store<PR>::get(K12, ((int64_t)(self * M + c) * MD + k * D + d) * NN + gn) * sS[a * D + d];
+      }
+      v = -gamma * v;
+      if (c == k) v += alpha;
+      Store<WP>::put(F, ((int64_t)(self * M + c) * M + k) * NN + gn, v);
+    }
   }
 }
 
