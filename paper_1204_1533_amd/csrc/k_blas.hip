@@ -86,6 +86,11 @@ __global__ void rk4_stage_kernel(double* __restrict__ Us, const double* __restri
   }
 }
 
+__global__ void copy_kernel(double* __restrict__ y, const double* __restrict__ x, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = x[i];
+}
+
 static unsigned grid_for(int64_t n, int nt) {
   int64_t g = (n + nt - 1) / nt;
   if (g > 8192) g = 8192;
@@ -126,6 +131,11 @@ hipError_t launch_axpby(double* y, double a, const double* x, double b, int64_t 
 hipError_t launch_rk4_stage(double* Us, const double* U, const double* K, double a, double* Acc, double b, int64_t n,
                             hipStream_t s) {
   hipLaunchKernelGGL(rk4_stage_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, Us, U, K, a, Acc, b, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(double* y, const double* x, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, y, x, n);
   return hipGetLastError();
 }
 

@@ -57,6 +57,15 @@ struct ldg_ctx_s {
   bool timing = false;
   Timed tm[3];  // 0 jacvec, 1 K21 gradient, 2 precond apply
   int krylov_avail = 0;  // Arnoldi vectors of the last GMRES cycle left in d_V
+  // RK4: one step captured as a HIP graph and replayed (launch-bound on small meshes)
+  hipStream_t rk_stream = nullptr;
+  hipEvent_t rk_ev[2] = {nullptr, nullptr};
+  hipGraph_t rk_graph = nullptr;
+  hipGraphExec_t rk_exec = nullptr;
+  const double* rk_U = nullptr;
+  const double* rk_S = nullptr;
+  const double* rk_gD = nullptr;
+  double rk_dt = 0.0;
   // learned correction of the preconditioner
   ldg_net net = nullptr;         // attached network (owned by the caller)
   int infer_prec = 2;            // precision of the network evaluation (F32 or BF16)

@@ -45,6 +45,8 @@ bool host_node_on_face(int node, int n, int side, int N1, int p, int* lidx) {
 
 extern "C" {
 
+static void rk4_drop_graph(ldg_ctx c);
+
 const char* ldg_status_string(ldg_status s) {
   switch (s) {
     case LDG_OK: return "ok";
@@ -72,6 +74,10 @@ void ldg_destroy(ldg_ctx c) {
   for (void* p : ptrs)
     if (p) hipFree(p);
   learned_free(c);
+  rk4_drop_graph(c);
+  if (c->rk_stream) hipStreamDestroy(c->rk_stream);
+  for (hipEvent_t e : c->rk_ev)
+    if (e) hipEventDestroy(e);
   for (auto& t : c->tm)
     for (hipEvent_t e : t.ev) hipEventDestroy(e);
   delete c;
@@ -582,28 +588,73 @@ ldg_status ldg_newton_step(ldg_ctx c, double* U, const double* Ucomb, double alp
   return LDG_OK;
 }
 
-ldg_status ldg_rk4(ldg_ctx c, double* U, double dt, int32_t nsteps) {
-  if (!c) return LDG_E_INVALID;
-  if (!U || nsteps < 0 || !std::isfinite(dt)) return fail(c, LDG_E_INVALID, "arguments");
+// One classical RK4 step as kernel launches on dc.stream (kernels only, so the
+// sequence can be captured: the two copies are kernels, not copy nodes).
+static ldg_status rk4_step_launches(ldg_ctx c, double* U, double dt) {
   const DevCtx& dc = c->dc;
   const int64_t n = c->ndof;
-  TRY(dev_alloc(c, &c->d_R, (size_t)n));
-  TRY(dev_alloc(c, &c->d_tmp, (size_t)n));
-  TRY(dev_alloc(c, &c->d_Un, (size_t)n));
   double* Us = c->d_tmp;
   double* acc = c->d_Un;
   const double a[4] = {0.5 * dt, 0.5 * dt, dt, 0.0};
   const double b[4] = {dt / 6, dt / 3, dt / 3, dt / 6};
-  for (int s = 0; s < nsteps; ++s) {
-    HIPCK(c, hipMemcpyAsync(acc, U, sizeof(double) * n, hipMemcpyDeviceToDevice, dc.stream));
-    const double* cur = U;
-    for (int k = 0; k < 4; ++k) {
-      TRY(ldg_residual(c, cur, c->d_R, nullptr));
-      HIPCK(c, launch_rk4_stage(k < 3 ? Us : nullptr, U, c->d_R, a[k], acc, b[k], n, dc.stream));
-      cur = Us;
-    }
-    HIPCK(c, hipMemcpyAsync(U, acc, sizeof(double) * n, hipMemcpyDeviceToDevice, dc.stream));
+  HIPCK(c, launch_copy(acc, U, n, dc.stream));
+  const double* cur = U;
+  for (int k = 0; k < 4; ++k) {
+    TRY(ldg_residual(c, cur, c->d_R, nullptr));
+    HIPCK(c, launch_rk4_stage(k < 3 ? Us : nullptr, U, c->d_R, a[k], acc, b[k], n, dc.stream));
+    cur = Us;
   }
+  HIPCK(c, launch_copy(U, acc, n, dc.stream));
+  return LDG_OK;
+}
+
+static void rk4_drop_graph(ldg_ctx c) {
+  if (c->rk_exec) hipGraphExecDestroy(c->rk_exec);
+  if (c->rk_graph) hipGraphDestroy(c->rk_graph);
+  c->rk_exec = nullptr;
+  c->rk_graph = nullptr;
+}
+
+ldg_status ldg_rk4(ldg_ctx c, double* U, double dt, int32_t nsteps) {
+  if (!c) return LDG_E_INVALID;
+  if (!U || nsteps < 0 || !std::isfinite(dt)) return fail(c, LDG_E_INVALID, "arguments");
+  const int64_t n = c->ndof;
+  TRY(dev_alloc(c, &c->d_R, (size_t)n));
+  TRY(dev_alloc(c, &c->d_tmp, (size_t)n));
+  TRY(dev_alloc(c, &c->d_Un, (size_t)n));
+  if (nsteps == 0) return LDG_OK;
+  if (!c->rk_stream) {
+    HIPCK(c, hipStreamCreateWithFlags(&c->rk_stream, hipStreamNonBlocking));
+    HIPCK(c, hipEventCreateWithFlags(&c->rk_ev[0], hipEventDisableTiming));
+    HIPCK(c, hipEventCreateWithFlags(&c->rk_ev[1], hipEventDisableTiming));
+  }
+  // (re)capture one step when its kernel arguments change
+  if (!c->rk_exec || c->rk_U != U || c->rk_dt != dt || c->rk_S != c->dc.mp.S || c->rk_gD != c->dc.mp.gD) {
+    rk4_drop_graph(c);
+    const hipStream_t caller = c->dc.stream;
+    c->dc.stream = c->rk_stream;
+    hipError_t e = hipStreamBeginCapture(c->rk_stream, hipStreamCaptureModeThreadLocal);
+    ldg_status st = e == hipSuccess ? rk4_step_launches(c, U, dt) : LDG_E_HIP;
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(c->rk_stream, &g) : e;
+    c->dc.stream = caller;
+    if (st != LDG_OK || e2 != hipSuccess) {
+      if (g) hipGraphDestroy(g);
+      return st != LDG_OK ? st : fail(c, LDG_E_HIP, std::string("RK4 graph capture: ") + hipGetErrorString(e2));
+    }
+    c->rk_graph = g;
+    HIPCK(c, hipGraphInstantiate(&c->rk_exec, g, nullptr, nullptr, 0));
+    c->rk_U = U;
+    c->rk_dt = dt;
+    c->rk_S = c->dc.mp.S;
+    c->rk_gD = c->dc.mp.gD;
+  }
+  // caller's stream -> graph stream -> caller's stream
+  HIPCK(c, hipEventRecord(c->rk_ev[0], c->dc.stream));
+  HIPCK(c, hipStreamWaitEvent(c->rk_stream, c->rk_ev[0], 0));
+  for (int s = 0; s < nsteps; ++s) HIPCK(c, hipGraphLaunch(c->rk_exec, c->rk_stream));
+  HIPCK(c, hipEventRecord(c->rk_ev[1], c->rk_stream));
+  HIPCK(c, hipStreamWaitEvent(c->dc.stream, c->rk_ev[1], 0));
   return LDG_OK;
 }
 

@@ -59,6 +59,7 @@ hipError_t launch_update(double* w, const double* V, int64_t ldv, int k, const d
 hipError_t launch_axpby(double* y, double a, const double* x, double b, int64_t n, hipStream_t s);  // y = a x + b y
 hipError_t launch_lincomb(double* y, const double* V, int64_t ldv, int k, const double* coef, int64_t n,
                           hipStream_t s);  // y += V coef
+hipError_t launch_copy(double* y, const double* x, int64_t n, hipStream_t s);  // y = x (a kernel, not a copy node)
 hipError_t launch_rk4_stage(double* Ustage, const double* U, const double* K, double a, double* Acc, double b,
                             int64_t n, hipStream_t s);
 

@@ -130,3 +130,29 @@ def test_rk4_parity_c2():
     tot1 = (U.cpu() * geo["J"][:, None, :] * w).sum(dim=(0, 2))
     assert torch.all((tot1 - tot0).abs() <= 1e-11 * tot0.abs())
     ctx.close()
+
+
+def test_rk4_graph_replays_match_oracle():
+    """RK4 runs as a captured graph replayed per step: repeated calls, with eager work and
+    synchronisations in between, and a new step size (a new capture) stay on the oracle's path."""
+    from oracle import solver
+    pr = case("ns2d_p2")
+    print("[gpu] rk4 graph replays ns2d_p2", flush=True)
+    ctx = gpu_of(pr)
+    orc = oracle_of(pr)
+    U = torch.as_tensor(pr.U0, device="cuda").contiguous()
+    R = torch.empty_like(U)
+    Uo = torch.as_tensor(pr.U0)
+    scale = float(Uo.abs().max())
+    for dt, calls in ((1e-3, 3), (5e-4, 2)):
+        for _ in range(calls):
+            ctx.ldg_rk4(U, dt, 2)
+            ctx.ldg_residual(U, R)  # eager work on the same stream between replays
+            torch.cuda.synchronize()
+            for _ in range(2):
+                Uo = solver.rk4_step(orc, Uo, dt)
+            err = float((U.cpu() - Uo).abs().max())
+            assert err <= 1e-12 * scale, (dt, err)
+            Ro = orc.residual(Uo)
+            assert float((R.cpu() - Ro).abs().max()) <= 1e-10 * float(Ro.abs().max())
+    ctx.close()
