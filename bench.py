@@ -35,6 +35,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=256, help="elements timed on the CPU oracle")
+    ap.add_argument("--no-rk4", action="store_true")
     return ap.parse_args()
 
 
@@ -105,6 +106,28 @@ def roofline(pr, reps, prec):
     return {"dominant": d, "all": allk}
 
 
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
+FLOPS_FILE = os.path.join(ROOT, "profiles", "residual_tgv32p4_fp64_flops.md")
+
+
+def counted_residual_flops():
+    """FP64 operations of one residual evaluation (gradient + residual kernels) from the committed
+    rocprofv3 VALU instruction counts, or None when the kernel source has changed since."""
+    import hashlib
+    import re
+    if not os.path.exists(FLOPS_FILE):
+        return None
+    txt = open(FLOPS_FILE).read()
+    m_f = re.search(r"residual_flops_per_eval\s*=\s*([0-9.eE+]+)", txt)
+    m_h = re.search(r"source_sha256\s*=\s*([0-9a-f]{64})", txt)
+    if not m_f or not m_h:
+        return None
+    src = os.path.join(ROOT, "paper_1204_1533_amd", "csrc", "k_resid.hip")
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != m_h.group(1):
+        return None
+    return float(m_f.group(1))
+
+
 def cpu_baseline(pr, n_sample):
     """The FP64 CPU oracle on a bounded sample: residual and Jacobian blocks of n_sample elements."""
     import numpy as np
@@ -126,6 +149,27 @@ def cpu_baseline(pr, n_sample):
     return {"value": dofs / dt, "unit": "DOF/s", "cores": torch.get_num_threads(), "kind": "oracle",
             "sample": f"residual + Jacobian blocks (K11, K12) of {len(el)} seeded elements of the workload, "
                       f"{dt:.1f} s"}
+
+
+def rk4_c2(Context):
+    """Explicit RK4 on the 2-D Euler vortex (32^2 perturbed quads, p=4, 102 k unknowns): each step
+    replays a captured graph of the 4 residual evaluations and stage updates."""
+    import torch
+    from ldg_workloads import configs
+    pr = configs.config2()
+    ctx = Context(pr.mesh, pr.equation, gamma=pr.gamma, stream=torch.cuda.current_stream().cuda_stream)
+    U = torch.as_tensor(pr.U0, device="cuda").contiguous()
+    ctx.ldg_rk4(U, pr.dt, 10)
+    torch.cuda.synchronize()
+    n = 100
+    t0 = time.perf_counter()
+    ctx.ldg_rk4(U, pr.dt, n)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / n
+    ctx.close()
+    log(f"[bench] C2 RK4: {ms:.3f} ms per step")
+    return {"workload": "2-D Euler isentropic vortex, 32x32 perturbed quads, p=4, 102400 unknowns",
+            "dt": pr.dt, "steps": n, "ms_per_step": ms, "residual_evals_dof_per_s": pr.n_dof * 4 / (ms * 1e-3)}
 
 
 def log(msg):
@@ -196,8 +240,15 @@ def main():
                      t_solve_ms=float(np.mean([p["t_solve_ms"] for p in prs])),
                      dU_rel_diff_vs_chosen=float((U - U_chosen).abs().max() / U.abs().max()))
 
+    rk4 = rk4_c2(Context) if not args.no_rk4 else None
     last = reps[-1]
     roof = roofline(pr, reps, chosen_prec)
+    fl = counted_residual_flops() if (pr.mesh.n_elem == 32768 and pr.mesh.p == 4) else None
+    if fl is not None:
+        tf = fl / (t_res * 1e-3) / 1e12
+        roof["all"]["residual"] = {"bound": "alu", "achieved": tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                   "frac": tf / FP64_PEAK_TFLOPS, "avg_ms": t_res, "flops_per_eval": fl,
+                                   "note": "gradient + residual kernels, FP64 operations counted by rocprofv3"}
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(pr, args.cpu_sample)
@@ -228,6 +279,7 @@ def main():
         "roofline": roof["dominant"],
         "kernels": roof["all"],
         "cpu_baseline": cpu,
+        "rk4_c2": rk4,
     }
     print(json.dumps(out), flush=True)
     ctx.close()
