@@ -344,8 +344,10 @@ static ldg_status norm2(ldg_ctx c, const double* w, double* out) {
 // Right-preconditioned GMRES(restart) on (alpha I - gamma A) x = b, x0 = 0,
 // classical Gram-Schmidt with one re-orthogonalisation.  The operator is the
 // stored split product (exact = false) or the exact tangent (exact = true).
+// true_res: end with the true residual ||b - A x|| in *est_res (else the
+// Arnoldi estimate; the refinement loop computes the exact residual itself).
 static ldg_status gmres(ldg_ctx c, const double* b, double* x, double rtol_abs, int restart, int max_iters,
-                        bool exact, int* iters, double* est_res) {
+                        bool exact, int* iters, double* est_res, bool true_res = true) {
   const DevCtx& dc = c->dc;
   const int64_t n = c->ndof;
   HIPCK(c, hipMemsetAsync(x, 0, sizeof(double) * n, dc.stream));
@@ -422,6 +424,7 @@ static ldg_status gmres(ldg_ctx c, const double* b, double* x, double rtol_abs, 
     HIPCK(c, launch_lincomb(c->d_tmp, c->d_V, n, k_used, c->d_h, n, dc.stream));
     TRY(precond_apply_any(c, c->d_tmp, c->d_z));
     HIPCK(c, launch_axpby(x, 1.0, c->d_z, 1.0, n, dc.stream));
+    if ((*est_res <= rtol_abs || its >= max_iters) && !true_res) break;
     if (*est_res <= rtol_abs || its >= max_iters) {
       // true residual for the report
       TRY(apply_op(c, x, c->d_tmp, exact));
@@ -520,7 +523,7 @@ ldg_status ldg_newton_step(ldg_ctx c, double* U, const double* Ucomb, double alp
     for (; sweeps < max_ref; ++sweeps) {
       int its;
       double est;
-      TRY(gmres(c, rr, c->d_x, inner * rn, o->restart, o->max_iters - total_its, false, &its, &est));
+      TRY(gmres(c, rr, c->d_x, inner * rn, o->restart, o->max_iters - total_its, false, &its, &est, false));
       total_its += its;
       HIPCK(c, launch_axpby(xacc, 1.0, c->d_x, 1.0, n, dc.stream));
       // exact residual rr = b - (alpha I - gamma A) xacc
