@@ -38,6 +38,7 @@ struct ldg_ctx_s {
   double* d_Qa = nullptr;  // D(U) at assembly
   // Newton / Krylov workspace
   double* d_V = nullptr;
+  double* d_Z = nullptr;  // preconditioned Arnoldi vectors z_k = P^{-1} v_k
   int cap_restart = 0;
   double* d_R = nullptr;
   double* d_G = nullptr;

@@ -69,7 +69,7 @@ int64_t ldg_num_dofs(ldg_ctx ctx) { return ctx ? ctx->ndof : -1; }
 void ldg_destroy(ldg_ctx c) {
   if (!c) return;
   void* ptrs[] = {c->d_xyz, c->d_face_nbr, c->d_nbr_node, c->d_sw, c->d_gD, c->d_S, c->d_Q, c->d_W, c->d_W2,
-                  c->d_K11, c->d_K12, c->d_F, c->d_Fem, c->d_Ua, c->d_Qa, c->d_V, c->d_R, c->d_G, c->d_x, c->d_r, c->d_z,
+                  c->d_K11, c->d_K12, c->d_F, c->d_Fem, c->d_Ua, c->d_Qa, c->d_V, c->d_Z, c->d_R, c->d_G, c->d_x, c->d_r, c->d_z,
                   c->d_tmp, c->d_Un, c->d_partial, c->d_h};
   for (void* p : ptrs)
     if (p) hipFree(p);
@@ -377,11 +377,12 @@ static ldg_status gmres(ldg_ctx c, const double* b, double* x, double rtol_abs, 
     for (int k = 0; k < restart; ++k) {
       double* vk = c->d_V + (int64_t)k * n;
       double* w = c->d_V + (int64_t)(k + 1) * n;
+      double* zk = c->d_Z + (int64_t)k * n;  // z_k = P^{-1} v_k is kept for the update of x
       {
         Span sp(c, 2);
-        TRY(precond_apply_any(c, vk, c->d_z));
+        TRY(precond_apply_any(c, vk, zk));
       }
-      TRY(apply_op(c, c->d_z, w, exact));
+      TRY(apply_op(c, zk, w, exact));
       // CGS2
       TRY(dots(c, c->d_V, k + 1, w, h.data()));
       HIPCK(c, hipMemcpyAsync(c->d_h, h.data(), sizeof(double) * (k + 1), hipMemcpyHostToDevice, dc.stream));
@@ -418,12 +419,9 @@ static ldg_status gmres(ldg_ctx c, const double* b, double* x, double rtol_abs, 
       for (int j = i + 1; j < k_used; ++j) s -= H[i * restart + j] * y[j];
       y[i] = s / H[i * restart + i];
     }
-    // x += P^{-1} (V y)
+    // x += P^{-1} (V y) = Z y  (P^{-1} is linear and the z_k were kept)
     HIPCK(c, hipMemcpyAsync(c->d_h, y.data(), sizeof(double) * k_used, hipMemcpyHostToDevice, dc.stream));
-    HIPCK(c, hipMemsetAsync(c->d_tmp, 0, sizeof(double) * n, dc.stream));
-    HIPCK(c, launch_lincomb(c->d_tmp, c->d_V, n, k_used, c->d_h, n, dc.stream));
-    TRY(precond_apply_any(c, c->d_tmp, c->d_z));
-    HIPCK(c, launch_axpby(x, 1.0, c->d_z, 1.0, n, dc.stream));
+    HIPCK(c, launch_lincomb(x, c->d_Z, n, k_used, c->d_h, n, dc.stream));
     if ((*est_res <= rtol_abs || its >= max_iters) && !true_res) break;
     if (*est_res <= rtol_abs || its >= max_iters) {
       // true residual for the report
@@ -443,9 +441,12 @@ static ldg_status ensure_krylov(ldg_ctx c, int restart) {
   if (restart < 1 || restart > 120) return fail(c, LDG_E_INVALID, "restart must be in 1..120");
   if (c->cap_restart < restart) {
     if (c->d_V) hipFree(c->d_V);
+    if (c->d_Z) hipFree(c->d_Z);
     c->d_V = nullptr;
+    c->d_Z = nullptr;
     c->cap_restart = 0;
     TRY(dev_alloc(c, &c->d_V, (size_t)(restart + 1) * n));
+    TRY(dev_alloc(c, &c->d_Z, (size_t)restart * n));
     c->cap_restart = restart;
   }
   TRY(dev_alloc(c, &c->d_R, (size_t)n));
