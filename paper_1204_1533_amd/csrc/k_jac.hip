@@ -146,17 +146,18 @@ __global__ void __launch_bounds__(NT_ELEM) jac_kernel(LineOps ops_arg, MeshParam
             G[a][b] = acc;
           }
         cofactor_row<D>(G, n, an);
-        double qd[VIS ? M * D : 1];
-        if constexpr (VIS) {
-#pragma unroll
-          for (int k = 0; k < M * D; ++k) {
-            double acc = 0.0;
-#pragma unroll
-            for (int t = 0; t < N1; ++t) acc += ops.I[g][t] * sQ[k * NP + line_node<D, N1>(n, l, t)];
-            qd[k] = acc;
-          }
-        }
         if (part == 0) {
+          // the gradient enters the state derivatives as a constant
+          double qd[VIS ? M * D : 1];
+          if constexpr (VIS) {
+#pragma unroll
+            for (int k = 0; k < M * D; ++k) {
+              double acc = 0.0;
+#pragma unroll
+              for (int t = 0; t < N1; ++t) acc += ops.I[g][t] * sQ[k * NP + line_node<D, N1>(n, l, t)];
+              qd[k] = acc;
+            }
+          }
           // d f / d u, one state component per pass (single-tangent duals);
           // the gradient is a constant here
           double ud[M];
@@ -240,10 +241,12 @@ __global__ void __launch_bounds__(NT_ELEM) jac_kernel(LineOps ops_arg, MeshParam
           for (int c = 0; c < M; ++c) uout[c] = mp.gD ? mp.gD[((e * 2 * D + f) * M + c) * NL + l] : 0.0;
         }
         if constexpr (VIS) {
+          if (part == 0) {  // the gradient derivatives do not involve q itself
 #pragma unroll
-          for (int k = 0; k < M * D; ++k) {
-            qin[k] = sQ[k * NP + nin];
-            qout[k] = (!bnd && S > 0) ? Q[(nb * QW + k) * NP + nd] : qin[k];
+            for (int k = 0; k < M * D; ++k) {
+              qin[k] = sQ[k * NP + nin];
+              qout[k] = (!bnd && S > 0) ? Q[(nb * QW + k) * NP + nd] : qin[k];
+            }
           }
         }
         // derivative with respect to the inside (side 0) and outside (side 1) variable
