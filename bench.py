@@ -179,8 +179,8 @@ def log(msg):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in "
-                                   "DESIGN.md and not built", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "runs on one GPU only: sharding the elements over several GPUs is not built",
+                          "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
     import torch

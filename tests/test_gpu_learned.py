@@ -301,7 +301,7 @@ def test_learned_gain_over_ilu0():
     """Train on solver-generated samples (12^3, p = 3 Navier-Stokes runs, seeds 0-7), then compare
     one BDF2 Newton step with and without the correction on held-out seeds 1000-1003.
 
-    The gain has no oracle (the paper has no learned part): the Newton residual judges the
+    The gain has no oracle (the paper has no learned part): the Newton residual measures the
     error, so both solves must reach the 1e-8 linear tolerance and give the same Newton
     residual, and the corrected preconditioner must need fewer GMRES iterations in total.
     """
