@@ -184,3 +184,35 @@ def test_training_lowers_the_loss_on_a_fixed_batch():
         for k in P:
             P[k], m1[k], m2[k] = LN.adam_step(P[k], g[k], m1[k], m2[k], step, lr=3e-3)
     assert float(L) < 0.5 * L0
+
+
+def test_bf16_emulated_gradient_is_the_exact_gradient_within_rounding():
+    """The BF16-emulated backward rounds features, weights, hidden activations and activation
+    gradients to bfloat16 (relative error at most 2^-9 each).  Its gradients must therefore agree
+    with central differences of the exact FP64 loss to within a few such roundings per factor of
+    each product (bound 4e-2 of the block's largest entry), while a wrong operand, sign or
+    transposition would be off by O(1)."""
+    d, At, pat, F, G = small_system()
+    X, Dinv, _ = LN.features(At, G)
+    n_in, n_out, H = X.shape[1], d.Np * d.m * d.m, 6
+    P = random_params(n_in, H, n_out, seed=11)
+    V = torch.randn(d.E, 2, d.m, d.Np, generator=torch.Generator().manual_seed(12), dtype=DT)
+    S, T = LN.probe_defects(At, F, pat, Dinv, V)
+    _, g16, _ = LN.loss_and_grad(P, X, At, S, T, bf16=True)
+    rng = np.random.default_rng(13)
+    for k, shp in LN.param_shapes(n_in, H, n_out):
+        flat = P[k].reshape(-1)
+        gk = g16[k].reshape(-1)
+        idxs = rng.choice(flat.numel(), size=min(16, flat.numel()), replace=False)
+        fds = []
+        for idx in idxs:
+            h = 1e-6 * max(1.0, abs(float(flat[idx])))
+            Pp = {kk: v.clone() for kk, v in P.items()}
+            Pm = {kk: v.clone() for kk, v in P.items()}
+            Pp[k].reshape(-1)[idx] += h
+            Pm[k].reshape(-1)[idx] -= h
+            fds.append(float(LN.loss_and_grad(Pp, X, At, S, T)[0] - LN.loss_and_grad(Pm, X, At, S, T)[0]) / (2 * h))
+        fds = np.array(fds)
+        an = gk[torch.as_tensor(idxs)].numpy()
+        scale = max(float(np.abs(fds).max()), 1e-12)
+        assert np.abs(an - fds).max() <= 4e-2 * scale, (k, np.abs(an - fds).max(), scale)

@@ -280,3 +280,52 @@ def test_relabelling_invariance(eq):
         Rback[e][:, ii + n1 * jj] = R2[perm[e]]
     assert np.abs(Rback - R).max() <= 1e-12 * np.abs(R).max()
     assert np.any(m2.switch_plus < 0)
+
+
+# ------------------------------------------------------------------ K21 weights = homogeneous gradient
+def flip_mesh(mesh, seed, frac=0.5):
+    """Reverse two local axes of a random subset of elements (a rotation by 180 degrees
+    in the plane of those axes), so that switch signs S = -1 and reversed face-node maps occur."""
+    rng = np.random.default_rng(seed)
+    E, D = mesh.n_elem, mesh.dim
+    flips = np.zeros((E, D), dtype=bool)
+    for e in np.nonzero(rng.random(E) < frac)[0]:
+        axes = rng.choice(D, size=2, replace=False)
+        flips[e, axes] = True
+    perm = rng.permutation(E)
+    return reorient_elements(mesh, flips, perm)
+
+
+def apply_k21(d, W, x):
+    """w[e, c, dd, a] = sum over slots of W[e, a, slot, dd] x[column node of the slot, c]."""
+    cols = d.column_nodes("K21")
+    E, m, Np = d.E, d.m, d.Np
+    xf = torch.as_tensor(x, dtype=torch.float64).reshape(E, m, Np).permute(0, 2, 1).reshape(E * Np, m)
+    c = torch.as_tensor(cols)
+    ok = (c >= 0)
+    xs = xf[torch.where(ok, c, torch.zeros_like(c))] * ok[..., None].to(torch.float64)  # [E, Np, ns, m]
+    return torch.einsum("easd,easc->ecda", W, xs)
+
+
+@pytest.mark.parametrize("kind", ["quad_dirichlet_flipped", "hex_periodic", "hex_flipped"])
+def test_k21_weights_apply_as_homogeneous_gradient(kind):
+    """The stored K21 weights (line slots and the switch-side neighbour slot) reproduce
+    D(x) with zero boundary data for any x (Section 4.1: K21 = dD/dU, D linear in U),
+    including elements whose local axes are reversed so that S = -1 occurs."""
+    if kind == "quad_dirichlet_flipped":
+        mesh = flip_mesh(quad_mesh(3, 3, 3, box=((0, 3), (0, 3)), perturb=0.2, seed=8), seed=9)
+    elif kind == "hex_periodic":
+        mesh = hex_mesh(2, 2)
+    else:
+        mesh = flip_mesh(hex_mesh(2, 2, amp=0.15), seed=10)
+    d = disc(mesh, EQ_NS, mu=0.05)
+    W = d.k21()
+    x = torch.randn(d.E, d.m, d.Np, generator=torch.Generator().manual_seed(4), dtype=torch.float64)
+    w = apply_k21(d, W, x)
+    ref = d.gradient(x, homogeneous=True)
+    assert float((w - ref).abs().max()) <= 1e-12 * float(ref.abs().max())
+    if kind != "hex_periodic":
+        assert np.any(mesh.switch_plus < 0)
+    # the Jacobian's own K21 output is the same operator
+    _, _, K21 = d.jacobian(fields.random_smooth_state(mesh, d.m, seed=5, base=base_state(mesh.dim), amp=0.05))
+    assert torch.allclose(K21, W, rtol=0, atol=1e-13 * float(W.abs().max()))

@@ -169,3 +169,73 @@ def test_dirk3_coefficients():
     b2 = (6 * a * a - 20 * a + 5) / 4
     assert abs(b1 + b2 + a - 1) < 1e-15
     assert abs(a ** 3 - 3 * a ** 2 + 1.5 * a - 1 / 6) < 1e-15
+
+
+# ------------------------------------------------------------------ A~ against its definition (Section 4.2)
+def _intra_element_columns(d, K11, K12, gamma, alpha, e):
+    """Columns of alpha I - gamma (K11_ee + K12_ee K21_ee) for element e, one unit vector at a
+    time: x = e_(b,k) on element e, w = D(x) with zero boundary data kept on element e only
+    (K21 taken inside the element), y = alpha x - gamma (K11 x + K12 w) read on element e."""
+    E, m, Np, D = d.E, d.m, d.Np, d.D
+    c11, c12 = d.column_nodes("K11"), d.column_nodes("K12")
+    out = torch.zeros(Np, m, Np, m, dtype=torch.float64)
+    for b in range(Np):
+        for k in range(m):
+            x = torch.zeros(E, m, Np, dtype=torch.float64)
+            x[e, k, b] = 1.0
+            w = d.gradient(x, homogeneous=True)
+            keep = torch.zeros(E, 1, 1, 1, dtype=torch.float64)
+            keep[e] = 1.0
+            w = (w * keep).reshape(E, m * D, Np)
+            y = alpha * x - gamma * (solver.blocks_apply(d, K11, c11, x, m) + solver.blocks_apply(d, K12, c12, w, m * D))
+            out[:, :, b, k] = y[e].T
+    return out
+
+
+def test_precond_matrix_is_the_masked_operator_of_an_isolated_element():
+    """A single element with Dirichlet faces couples to nothing else, so A = K11 + K12 K21 is
+    element-local and A~ must be alpha I - gamma A masked to the line pattern (Section 4.2)."""
+    mesh = hex_mesh(1, 2, length=1.0, periodic=False, amp=0.05)
+    ph = Physics(EQ_NS, 3, mu=0.05)
+    U = fields.random_smooth_state(mesh, 5, seed=3, base=[1.0, 0.3, -0.2, 0.1, 2.6], amp=0.05)
+    # Dirichlet data: a valid gas state (the inviscid boundary flux is Roe(g_D, u_in))
+    gD = fields.face_values(mesh, fields.random_smooth_state(mesh, 5, seed=4, base=[1.0, 0.2, 0.1, -0.1, 2.5],
+                                                               amp=0.05))
+    d = LineDG(3, 2, mesh.xyz, mesh.face_nbr, mesh.nbr_node, mesh.switch_plus, ph, 0.0, 10.0, None, gD)
+    K11, K12, K21 = d.jacobian(U)
+    gamma, alpha = 0.05, 1.0
+    At = solver.precond_matrix(d, K11, K12, K21, gamma, alpha)
+    Ad = solver.dense_operator(d, K11, K12, K21)  # [E m Np] ordering
+    Np, m = d.Np, d.m
+    A5 = torch.as_tensor(Ad).reshape(m, Np, m, Np).permute(1, 0, 3, 2)  # [a, c, b, k]
+    ref = alpha * torch.eye(Np * m, dtype=torch.float64).reshape(Np, m, Np, m) - gamma * A5
+    mask = torch.as_tensor(solver.line_pattern(d))[:, None, :, None].to(torch.float64)
+    assert torch.allclose(At[0], ref * mask, rtol=0, atol=1e-12 * float(ref.abs().max()))
+    # and the masked part is not trivially the whole operator: K12 K21 fills outside the pattern
+    assert float((ref * (1 - mask)).abs().max()) > 1e-6
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_precond_matrix_is_the_intra_element_restriction(dim):
+    """On a periodic mesh with reversed element axes (S = -1 faces), A~_e equals the line-pattern
+    mask of alpha I - gamma (K11_ee + K12_ee K21_ee), built here from the split product with the
+    gradient of unit vectors kept inside the element."""
+    from tests.test_oracle_linedg import flip_mesh
+    if dim == 2:
+        mesh = flip_mesh(quad_mesh(3, 3, 2, box=((0, 3), (0, 3)), periodic=(True, True), perturb=0.2, seed=1), 2)
+        base = [1.0, 0.3, -0.2, 2.6]
+    else:
+        mesh = flip_mesh(hex_mesh(2, 1, amp=0.15), 3)
+        base = [1.0, 0.3, -0.2, 0.1, 2.6]
+    ph = Physics(EQ_NS, dim, mu=0.05)
+    d = LineDG(dim, mesh.p, mesh.xyz, mesh.face_nbr, mesh.nbr_node, mesh.switch_plus, ph)
+    U = fields.random_smooth_state(mesh, d.m, seed=4, base=base, amp=0.05)
+    K11, K12, K21 = d.jacobian(U)
+    gamma, alpha = 0.05, 1.0
+    At = solver.precond_matrix(d, K11, K12, K21, gamma, alpha)
+    mask = torch.as_tensor(solver.line_pattern(d))[:, None, :, None].to(torch.float64)
+    flipped = np.nonzero((mesh.switch_plus < 0).any(1))[0]
+    assert len(flipped) > 0
+    for e in sorted({0, int(flipped[0]), d.E - 1}):
+        ref = _intra_element_columns(d, K11, K12, gamma, alpha, e) * mask
+        assert torch.allclose(At[e], ref, rtol=0, atol=1e-12 * float(ref.abs().max())), e
