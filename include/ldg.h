@@ -11,7 +11,9 @@
  * Conventions shared by every call
  * --------------------------------
  *  - Every call returns an ldg_status; no C++ exception crosses the ABI.  On
- *    failure ldg_last_error(ctx) returns a message (thread-unsafe, per ctx).
+ *    failure ldg_last_error(ctx) returns a message (thread-unsafe, per ctx);
+ *    ldg_last_error(NULL) returns the message of this thread's last failed
+ *    ldg_create.
  *  - Arrays named *_dev are device pointers owned by the caller (e.g. torch
  *    tensors on cuda:0), contiguous, float64, in the documented layout.  They
  *    must not alias unless a call says so.  Arrays named *_host are host
@@ -24,9 +26,11 @@
  *    nodes are numbered by the direction-n reference lines that end on it (the
  *    other reference coordinates in increasing dimension order, lowest fastest).
  *  - All device work is ordered on the stream given to ldg_create.  Calls do
- *    not synchronise the host unless stated (ldg_newton_step does).
+ *    not synchronise the host unless stated (ldg_newton_step and
+ *    ldg_implicit_step do).
  *  - The context owns all internal device memory; it is allocated by
- *    ldg_create and grown by ldg_jacobian_assemble, and released by ldg_destroy.
+ *    ldg_create, grown by the first call that needs more (assembly, products,
+ *    Newton and time steps), and released by ldg_destroy.
  */
 #ifndef LDG_H
 #define LDG_H
@@ -123,9 +127,13 @@ ldg_status ldg_jacobian_assemble(ldg_ctx ctx, const double* U_dev, double alpha,
  * Error: LDG_E_NOT_ASSEMBLED. */
 ldg_status ldg_jacvec(ldg_ctx ctx, const double* x_dev, double* y_dev, int32_t exact_fp64);
 
-/* z = P^{-1} r with the block ILU(0) factors of A~ (per element, forward and
- * backward block substitution), plus the learned correction when the current
- * assembly applies one.  r_dev, z_dev [E][m][Np], may not alias.
+/* Preconditioner of Section 4.2: the block-Jacobi matrix A~ that keeps A only
+ * on each element's line pattern (no K12 K21 fill, no inter-element
+ * coupling), applied as z = P^{-1} r with its block ILU(0) factors (per
+ * element, forward and backward block substitution in natural node order; the
+ * paper factorises each block by a sparse direct LU and names ILU as an
+ * improvement), plus the learned correction when the current assembly applies
+ * one.  Linear in r.  r_dev, z_dev [E][m][Np], may not alias.
  * Error: LDG_E_NOT_ASSEMBLED. */
 ldg_status ldg_precond_apply(ldg_ctx ctx, const double* r_dev, double* z_dev);
 
@@ -166,16 +174,81 @@ typedef struct {
   int32_t n_jacvec, n_k21, n_precond;
 } ldg_solver_report;
 
-/* One Newton step on G(U) = alpha (U - Ucomb) - gamma R(U) (BDF2:
- * Ucomb = (4U^n - U^{n-1})/3, gamma = 2 dt/3, alpha = 1; steady: alpha = 0,
- * gamma = 1): solve (alpha I - gamma A) dU = -G(U) by right-preconditioned
- * GMRES(restart) with the split product and BILU(0); with storage_prec !=
- * LDG_F64 the solve is wrapped in FP64 iterative refinement using the exact
- * tangent product.  U_dev (in/out) [E][m][Np]; Ucomb_dev may be NULL (zero).
+/* One Newton step of Section 4.2 (eqs. dirkeqn, fulldiscprimal) on
+ * G(U) = alpha (U - Ucomb) - gamma R(U): solve (alpha I - gamma A) dU = -G(U)
+ * with A = K11 + K12 K21, by right-preconditioned GMRES(restart) with the
+ * split product (eq. matvecsplit) and the preconditioner of
+ * ldg_precond_apply, then U += dU.  The paper's DIRK stage has alpha = 1,
+ * gamma = alpha_dirk dt; BDF2: Ucomb = (4U^n - U^{n-1})/3, gamma = 2 dt/3;
+ * steady: alpha = 0, gamma = 1.  With storage_prec != LDG_F64 the solve is
+ * wrapped in FP64 iterative refinement using the exact tangent product.
+ * The learned correction, when used, is judged by the outcome: if its solve
+ * misses rtol, or the step does not lower ||G||, the step is repeated with the
+ * plain BILU(0) factors and report->fallback_used is set.
+ * U_dev (in/out) [E][m][Np]; Ucomb_dev may be NULL (zero), must not alias U.
  * Synchronises the stream.  On LDG_E_NOT_CONVERGED / LDG_E_NONFINITE, U is
  * unchanged and report says why. */
 ldg_status ldg_newton_step(ldg_ctx ctx, double* U_dev, const double* Ucomb_dev, double alpha,
                            double gamma, const ldg_solver_opts* opts, ldg_solver_report* report);
+
+/* Implicit time steps (Section 4.1) driven by Newton iterations of
+ * ldg_newton_step's kind on each stage equation Y - Ucomb - gamma F(Y) = 0:
+ *  LDG_DIRK3          Alexander's L-stable three-stage, third-order DIRK
+ *                     (eqs. dirk1, dirk2) with alpha = 0.435866521508459,
+ *                     tau_2 = (1 + alpha)/2, b_1 = -(6 alpha^2 - 16 alpha + 1)/4,
+ *                     b_2 = (6 alpha^2 - 20 alpha + 5)/4; every stage has
+ *                     gamma = alpha dt, so one Jacobian serves all stages;
+ *                     U^{n+1} = Y_3 (the last tableau row equals b);
+ *  LDG_BDF2           Ucomb = (4U^n - U^{n-1})/3, gamma = 2 dt/3;
+ *  LDG_BACKWARD_EULER Ucomb = U^n, gamma = dt (pseudo-time to a steady state).
+ * Jacobian re-use (Section 4.3): with reuse != 0 the assembled K11, K12 and
+ * preconditioner are kept across Newton iterations, stages and steps as long
+ * as gamma and the storage precision stay the same, and re-assembled at the
+ * current iterate when a stage has taken reassemble_after Newton iterations
+ * since the last assembly (the paper uses 15, with 5 GMRES iterations per
+ * Newton iteration).  A stage has converged when
+ * ||G|| <= max(newton_rtol ||G(Y_start)||, newton_atol); with both zero every
+ * stage runs exactly max_newton Newton iterations and accepts the result (a
+ * linearly implicit scheme when max_newton = 1).
+ * With gmres_per_newton > 0 every Newton iteration runs that many GMRES
+ * iterations on the stored operator (no refinement: the FP64 Newton residual
+ * corrects the low-precision solve); with 0 each linear solve runs to
+ * lin_opts->rtol as in ldg_newton_step.  lin_opts->reassemble is ignored.
+ * U_dev (in/out) [E][m][Np].  Uprev_dev: BDF2 history U^{n-1} (in), replaced by
+ * U^n on success; NULL starts BDF2 with U^{n-1} = U^n; unused otherwise.
+ * Work arrays are allocated by the first call.  Synchronises the stream.
+ * On failure U (and Uprev) are unchanged and the report says where it stopped.
+ * Errors: LDG_E_INVALID, LDG_E_NOT_CONVERGED, LDG_E_NONFINITE. */
+typedef enum { LDG_BDF2 = 0, LDG_DIRK3 = 1, LDG_BACKWARD_EULER = 2 } ldg_scheme;
+
+typedef struct {
+  int32_t scheme;           /* ldg_scheme                                          */
+  int32_t max_newton;       /* Newton iterations allowed per stage (>= 1)          */
+  double newton_rtol;       /* stage tolerance relative to ||G|| at its start      */
+  double newton_atol;       /* absolute stage tolerance                            */
+  int32_t gmres_per_newton; /* fixed GMRES iterations per Newton iteration, 0 = to rtol */
+  int32_t reuse;            /* keep the assembled Jacobian across iterations/stages/steps */
+  int32_t reassemble_after; /* with reuse: re-assemble after this many Newton iterations of a stage */
+} ldg_step_opts;
+
+typedef struct {
+  int32_t stages;           /* stages attempted                                   */
+  int32_t newton_iters;     /* Newton iterations over all stages                  */
+  int32_t max_stage_newton; /* most Newton iterations in one stage                */
+  int32_t assemblies;       /* Jacobian assemblies during the step                */
+  int32_t gmres_iters;      /* GMRES iterations over the step                     */
+  int32_t converged;
+  int32_t fallback_used;    /* the learned correction was rejected at least once   */
+  double newton_res_first;  /* ||G|| at the start of the first stage              */
+  double newton_res_final;  /* ||G|| after the last Newton iteration              */
+  double lin_relres_max;    /* largest relative linear residual of a Newton solve  */
+  double t_assemble_ms;     /* stream-timed assemblies, summed                    */
+  double t_solve_ms;        /* stream-timed linear solves, summed                 */
+  double t_ms;              /* host wall time of the step                         */
+} ldg_step_report;
+
+ldg_status ldg_implicit_step(ldg_ctx ctx, double* U_dev, double* Uprev_dev, double dt, const ldg_step_opts* opts,
+                             const ldg_solver_opts* lin_opts, ldg_step_report* report);
 
 /* Classical four-stage Runge-Kutta on dU/dt = R(U) (Section 4.1), n_steps
  * steps of size dt, U_dev in/out [E][m][Np]. */

@@ -17,7 +17,8 @@ TEST INFRASTRUCTURE ONLY: part of the plain FP64 CPU oracle.
   exact-block reference.
 * GMRES (Saad and Schultz) with right preconditioning, x0 = 0, restart m,
   modified Gram-Schmidt, Givens rotations; stop when ||b - A x|| <= rtol ||b||.
-* Classical four-stage Runge-Kutta (Section 4.1).
+* Classical four-stage Runge-Kutta and the three-stage DIRK with Newton
+  stage solves (Section 4.1).
 """
 from __future__ import annotations
 
@@ -237,6 +238,53 @@ def newton_step(d: LineDG, U, Ucomb, gamma, alpha=1.0, rtol=1e-8, restart=50, ma
     G1 = alpha * (U1 - Uc) - gamma * d.residual(U1)
     return NewtonResult(U=U1, iters=its, lin_relres=rel, G0=float(torch.linalg.norm(G0)),
                         G1=float(torch.linalg.norm(G1)), dU=dU.reshape(U.shape))
+
+
+# Alexander's L-stable, three-stage, third-order DIRK (Section 4.1, eqs. dirk1, dirk2)
+DIRK3_ALPHA = 0.435866521508459
+
+
+def dirk3_tableau():
+    """(A, b): a_ii = alpha, c_2 = tau_2 = (1 + alpha)/2, last row of A equal to b."""
+    a = DIRK3_ALPHA
+    tau2 = (1.0 + a) / 2.0
+    b1 = -(6 * a * a - 16 * a + 1) / 4
+    b2 = (6 * a * a - 20 * a + 5) / 4
+    A = [[a, 0.0, 0.0], [tau2 - a, a, 0.0], [b1, b2, a]]
+    return A, [b1, b2, a]
+
+
+def dirk3_step(d: LineDG, U, dt, newton_tol=1e-12, max_newton=20, rtol=1e-12, restart=50):
+    """One DIRK3 step: K_i = F(U_n + dt sum_j a_ij K_j), U_{n+1} = U_n + dt sum_j b_j K_j.
+
+    Each stage solves Y_i - (U_n + dt sum_{j<i} a_ij K_j) - dt a_ii F(Y_i) = 0 by
+    Newton's method (newton_step, a fresh Jacobian every iteration) until
+    ||G|| <= newton_tol ||G(Y start)||, then K_i = F(Y_i).  Returns (U_{n+1}, stats).
+    """
+    A, b = dirk3_tableau()
+    U = torch.as_tensor(U, dtype=DT).reshape(d.E, d.m, d.Np)
+    K = []
+    Y = U.clone()
+    newton = []
+    for i in range(3):
+        Ucomb = U.clone()
+        for j in range(i):
+            Ucomb = Ucomb + dt * A[i][j] * K[j]
+        gamma = dt * A[i][i]
+        G0 = None
+        for it in range(max_newton):
+            res = newton_step(d, Y, Ucomb, gamma, rtol=rtol, restart=restart)
+            if G0 is None:
+                G0 = res["G0"]
+            Y = res["U"]
+            if res["G1"] <= newton_tol * G0:
+                break
+        newton.append(it + 1)
+        K.append(d.residual(Y))
+    U1 = U.clone()
+    for j in range(3):
+        U1 = U1 + dt * b[j] * K[j]
+    return U1, {"newton": newton}
 
 
 def rk4_step(d: LineDG, U, dt):

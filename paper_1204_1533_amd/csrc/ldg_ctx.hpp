@@ -47,6 +47,12 @@ struct ldg_ctx_s {
   double* d_z = nullptr;
   double* d_tmp = nullptr;
   double* d_Un = nullptr;
+  double* d_Uold = nullptr;  // state before a Newton update (undone when the learned correction is rejected)
+  int n_assemblies = 0;      // Jacobian assemblies since creation
+  // implicit time-step driver: U^n, the stage's explicit part, dt K_1 and dt K_2 (DIRK)
+  double* d_st_Un = nullptr;
+  double* d_st_comb = nullptr;
+  double* d_st_K = nullptr;
   double* d_partial = nullptr;
   double* d_h = nullptr;
   int nblk_dot = 0;
@@ -174,6 +180,9 @@ inline size_t elem_size(int prec) { return prec == LDG_F64 ? 8 : (prec == LDG_F3
     ldg_status s_ = (x);           \
     if (s_ != LDG_OK) return s_;   \
   } while (0)
+
+// y = (alpha I - gamma A) x with the caller's buffer W for w = K21 x (ldg_host.cpp)
+ldg_status apply_op_with(ldg_ctx c, const double* x, double* y, bool exact, double* W);
 
 // learned-correction hooks (ldg_learned.cpp)
 ldg_status learned_after_form(ldg_ctx c, const double* R_at_U, double gamma);

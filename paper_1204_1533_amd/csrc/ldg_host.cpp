@@ -2,6 +2,7 @@
 // the Newton-GMRES driver (Section 4.2 of the paper).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -62,7 +63,10 @@ const char* ldg_status_string(ldg_status s) {
   return "unknown status";
 }
 
-const char* ldg_last_error(ldg_ctx ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+// Message of the last failed ldg_create on this thread (no context exists then).
+static thread_local std::string g_create_err;
+
+const char* ldg_last_error(ldg_ctx ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
 
 int64_t ldg_num_dofs(ldg_ctx ctx) { return ctx ? ctx->ndof : -1; }
 
@@ -70,7 +74,7 @@ void ldg_destroy(ldg_ctx c) {
   if (!c) return;
   void* ptrs[] = {c->d_xyz, c->d_face_nbr, c->d_nbr_node, c->d_sw, c->d_gD, c->d_S, c->d_Q, c->d_W, c->d_W2,
                   c->d_K11, c->d_K12, c->d_F, c->d_Fem, c->d_Ua, c->d_Qa, c->d_V, c->d_Z, c->d_R, c->d_G, c->d_x, c->d_r, c->d_z,
-                  c->d_tmp, c->d_Un, c->d_partial, c->d_h};
+                  c->d_tmp, c->d_Un, c->d_partial, c->d_h, c->d_Uold, c->d_st_Un, c->d_st_comb, c->d_st_K};
   for (void* p : ptrs)
     if (p) hipFree(p);
   learned_free(c);
@@ -84,26 +88,32 @@ void ldg_destroy(ldg_ctx c) {
 }
 
 ldg_status ldg_create(const ldg_problem_desc* d, void* stream, ldg_ctx* out) {
-  if (!out) return LDG_E_INVALID;
+  g_create_err.clear();
+  if (!out) {
+    g_create_err = "null output handle";
+    return LDG_E_INVALID;
+  }
   *out = nullptr;
-  if (!d) return LDG_E_INVALID;
+  if (!d) {
+    g_create_err = "null problem description";
+    return LDG_E_INVALID;
+  }
   ldg_ctx c = new ldg_ctx_s();
   auto bad = [&](ldg_status s, const std::string& m) {
-    std::string msg = m;
+    g_create_err = "ldg_create: " + m + (c->err.empty() ? std::string() : " (" + c->err + ")");
     ldg_destroy(c);
-    (void)msg;
     return s;
   };
-  if (d->dim != 2 && d->dim != 3) return bad(LDG_E_UNSUPPORTED, "dim");
-  if (d->p < 1 || d->p > 4) return bad(LDG_E_UNSUPPORTED, "p");
-  if (d->equation < 0 || d->equation > 2) return bad(LDG_E_UNSUPPORTED, "equation");
-  if (d->node_family != 0 && d->node_family != 1) return bad(LDG_E_INVALID, "node_family");
-  if (d->n_elem < 1) return bad(LDG_E_INVALID, "n_elem");
+  if (d->dim != 2 && d->dim != 3) return bad(LDG_E_UNSUPPORTED, "dim must be 2 or 3");
+  if (d->p < 1 || d->p > 4) return bad(LDG_E_UNSUPPORTED, "p must be in 1..4");
+  if (d->equation < 0 || d->equation > 2) return bad(LDG_E_UNSUPPORTED, "equation must be 0 (Poisson), 1 (Euler) or 2 (Navier-Stokes)");
+  if (d->node_family != 0 && d->node_family != 1) return bad(LDG_E_INVALID, "node_family must be 0 or 1");
+  if (d->n_elem < 1) return bad(LDG_E_INVALID, "n_elem must be positive");
   if (!d->node_xyz_host || !d->face_nbr_host || !d->nbr_node_host || !d->switch_plus_host)
     return bad(LDG_E_INVALID, "null mesh array");
-  if (d->equation != LDG_POISSON && !(d->gamma > 1.0)) return bad(LDG_E_INVALID, "gamma");
-  if (d->equation == LDG_NS && (d->mu < 0.0 || !(d->prandtl > 0.0))) return bad(LDG_E_INVALID, "mu/prandtl");
-  if (d->c11_interior < 0.0 || d->c11_dirichlet < 0.0) return bad(LDG_E_INVALID, "c11");
+  if (d->equation != LDG_POISSON && !(d->gamma > 1.0)) return bad(LDG_E_INVALID, "gamma must exceed 1");
+  if (d->equation == LDG_NS && (d->mu < 0.0 || !(d->prandtl > 0.0))) return bad(LDG_E_INVALID, "mu must be >= 0 and prandtl > 0");
+  if (d->c11_interior < 0.0 || d->c11_dirichlet < 0.0) return bad(LDG_E_INVALID, "c11 penalties must be >= 0");
   const int D = d->dim, P = d->p, N1 = P + 1;
   const int NP = (int)ipow64(N1, D), NL = (int)ipow64(N1, D - 1);
   const int64_t E = d->n_elem;
@@ -113,19 +123,20 @@ ldg_status ldg_create(const ldg_problem_desc* d, void* stream, ldg_ctx* out) {
   for (int64_t e = 0; e < E; ++e) {
     for (int n = 0; n < D; ++n) {
       const int8_t sp = d->switch_plus_host[e * D + n];
-      if (sp != 1 && sp != -1) return bad(LDG_E_INVALID, "switch_plus must be +-1");
+      if (sp != 1 && sp != -1)
+        return bad(LDG_E_INVALID, "switch_plus must be +-1 (element " + std::to_string(e) + ")");
       for (int s = 0; s < 2; ++s) {
         const int f = 2 * n + s;
         const int64_t nb = d->face_nbr_host[e * 2 * D + f];
-        if (nb >= E) return bad(LDG_E_SHAPE, "face_nbr out of range");
+        if (nb >= E) return bad(LDG_E_SHAPE, std::string("face_nbr out of range") + " (element " + std::to_string(e) + ", face " + std::to_string(f) + ")");
         if (nb < 0) {
-          if (nb != -1) return bad(LDG_E_UNSUPPORTED, "only boundary tag 0 (Dirichlet) is built");
+          if (nb != -1) return bad(LDG_E_UNSUPPORTED, std::string("only boundary tag 0 (Dirichlet) is built") + " (element " + std::to_string(e) + ", face " + std::to_string(f) + ")");
           any_dirichlet = true;
           continue;
         }
         for (int l = 0; l < NL; ++l) {
           const int nd = d->nbr_node_host[(e * 2 * D + f) * NL + l];
-          if (nd < 0 || nd >= NP) return bad(LDG_E_SHAPE, "nbr_node out of range");
+          if (nd < 0 || nd >= NP) return bad(LDG_E_SHAPE, std::string("nbr_node out of range") + " (element " + std::to_string(e) + ", face " + std::to_string(f) + ")");
           const int mine = host_line_node(n, l, s ? P : 0, N1);
           // find the neighbour face that holds nd and maps back to us
           bool found = false;
@@ -137,10 +148,11 @@ ldg_status ldg_create(const ldg_problem_desc* d, void* stream, ldg_ctx* out) {
             const int Smine = s ? sp : -sp;
             const int8_t sp2 = d->switch_plus_host[nb * D + f2 / 2];
             const int Sther = (f2 % 2) ? sp2 : -sp2;
-            if (Smine != -Sther) return bad(LDG_E_SHAPE, "switch signs must be opposite across a face");
+            if (Smine != -Sther)
+              return bad(LDG_E_SHAPE, std::string("switch signs must be opposite across a face") + " (element " + std::to_string(e) + ", face " + std::to_string(f) + ")");
             found = true;
           }
-          if (!found) return bad(LDG_E_SHAPE, "face connectivity is not reciprocal");
+          if (!found) return bad(LDG_E_SHAPE, std::string("face connectivity is not reciprocal") + " (element " + std::to_string(e) + ", face " + std::to_string(f) + ")");
         }
       }
     }
@@ -158,7 +170,7 @@ ldg_status ldg_create(const ldg_problem_desc* d, void* stream, ldg_ctx* out) {
   dc.NG = n_gauss(P);
   dc.E = E;
   dc.stream = (hipStream_t)stream;
-  if (!build_line_ops(P, d->node_family, dc.ops, nullptr)) return bad(LDG_E_UNSUPPORTED, "p");
+  if (!build_line_ops(P, d->node_family, dc.ops, nullptr)) return bad(LDG_E_UNSUPPORTED, "1-D operators for this p");
   c->ndof = E * M * NP;
   c->nq = c->ndof * D;
   c->nnode = E * NP;
@@ -167,13 +179,13 @@ ldg_status ldg_create(const ldg_problem_desc* d, void* stream, ldg_ctx* out) {
       (st = dev_alloc(c, &c->d_face_nbr, (size_t)E * 2 * D)) != LDG_OK ||
       (st = dev_alloc(c, &c->d_nbr_node, (size_t)E * 2 * D * NL)) != LDG_OK ||
       (st = dev_alloc(c, &c->d_sw, (size_t)E * D)) != LDG_OK || (st = dev_alloc(c, &c->d_Q, (size_t)c->nq)) != LDG_OK)
-    return bad(st, "alloc");
+    return bad(st, "device allocation of the mesh arrays");
   if (hipMemcpy(c->d_xyz, d->node_xyz_host, sizeof(double) * E * D * NP, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->d_face_nbr, d->face_nbr_host, sizeof(int64_t) * E * 2 * D, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->d_nbr_node, d->nbr_node_host, sizeof(int32_t) * E * 2 * D * NL, hipMemcpyHostToDevice) !=
           hipSuccess ||
       hipMemcpy(c->d_sw, d->switch_plus_host, sizeof(int8_t) * E * D, hipMemcpyHostToDevice) != hipSuccess)
-    return bad(LDG_E_HIP, "copy");
+    return bad(LDG_E_HIP, "copy of the mesh arrays to the device");
   MeshParams& mp = dc.mp;
   mp.E = E;
   mp.gamma = d->gamma;
@@ -278,23 +290,34 @@ ldg_status ldg_jacobian_assemble(ldg_ctx c, const double* U, double alpha, doubl
   return assemble(c, U, alpha, gamma, prec, nullptr);
 }
 
-static ldg_status apply_op(ldg_ctx c, const double* x, double* y, bool exact) {
+}  // extern "C"
+
+namespace ldg_host {
+// y = (alpha I - gamma A) x with w = K21 x held in W (nq doubles, unused for Euler).
+ldg_status apply_op_with(ldg_ctx c, const double* x, double* y, bool exact, double* W) {
   const DevCtx& dc = c->dc;
-  TRY(dev_alloc(c, &c->d_W, (size_t)c->nq));
   const bool vis = dc.EQ != LDG_EULER;
   if (vis) {
     Span sp(c, 1);
-    HIPCK(c, launch_gradient(dc, x, c->d_W, true));
+    HIPCK(c, launch_gradient(dc, x, W, true));
   }
   if (exact) {
     // y = alpha x - gamma dR/dU x  (tangent of the FP64 residual at the assembled state)
-    HIPCK(c, launch_residual_tangent(dc, c->d_Ua, x, vis ? c->d_Qa : nullptr, vis ? c->d_W : nullptr, y));
+    HIPCK(c, launch_residual_tangent(dc, c->d_Ua, x, vis ? c->d_Qa : nullptr, vis ? W : nullptr, y));
     HIPCK(c, launch_axpby(y, c->alpha, x, -c->gamma, c->ndof, dc.stream));
   } else {
     Span sp(c, 0);
-    HIPCK(c, launch_jacvec(dc, c->d_K11, c->d_K12, c->prec, c->alpha, c->gamma, x, vis ? c->d_W : nullptr, y));
+    HIPCK(c, launch_jacvec(dc, c->d_K11, c->d_K12, c->prec, c->alpha, c->gamma, x, vis ? W : nullptr, y));
   }
   return LDG_OK;
+}
+}  // namespace ldg_host
+
+extern "C" {
+
+static ldg_status apply_op(ldg_ctx c, const double* x, double* y, bool exact) {
+  TRY(dev_alloc(c, &c->d_W, (size_t)c->nq));
+  return apply_op_with(c, x, y, exact, c->d_W);
 }
 
 ldg_status ldg_jacvec(ldg_ctx c, const double* x, double* y, int32_t exact) {
@@ -462,13 +485,97 @@ static ldg_status ensure_krylov(ldg_ctx c, int restart) {
   return LDG_OK;
 }
 
-ldg_status ldg_newton_step(ldg_ctx c, double* U, const double* Ucomb, double alpha, double gamma,
-                           const ldg_solver_opts* o, ldg_solver_report* rep) {
+// G(U) = alpha (U - Ucomb) - gamma R(U) into G (R(U) into d_R) and ||G||_2.
+static ldg_status eval_G(ldg_ctx c, const double* U, const double* Ucomb, double alpha, double gamma, double* G,
+                         double* gnorm) {
+  const DevCtx& dc = c->dc;
+  const int64_t n = c->ndof;
+  TRY(ldg_residual(c, U, c->d_R, nullptr));
+  HIPCK(c, launch_copy(G, U, n, dc.stream));
+  if (Ucomb) HIPCK(c, launch_axpby(G, -1.0, Ucomb, 1.0, n, dc.stream));
+  HIPCK(c, launch_axpby(G, -gamma, c->d_R, alpha, n, dc.stream));
+  TRY(norm2(c, G, gnorm));
+  return LDG_OK;
+}
+
+// Internal controls of one Newton iteration (the public ldg_newton_step uses
+// the defaults; the time-step driver sets them).
+struct NewtonCtl {
+  bool G_current = false;       // d_R = R(U) and d_G = G(U) already hold on entry
+  bool accept_inexact = false;  // update U even when the linear solve stops short of rtol
+  bool refine = true;           // FP64 refinement around low-precision storage
+  bool true_res = true;         // end the (unrefined) GMRES with the true residual
+};
+
+// Solves (alpha I - gamma A) x = b with b = d_G into d_x: plain GMRES on the
+// stored operator (FP64 storage, or no refinement asked), otherwise FP64
+// iterative refinement with the exact tangent around GMRES on the stored one.
+static ldg_status linear_solve(ldg_ctx c, const ldg_solver_opts* o, const NewtonCtl& ctl, double bnorm,
+                               int* total_its, int* sweeps_out, double* res_out, bool* ok_out) {
+  const DevCtx& dc = c->dc;
+  const int64_t n = c->ndof;
+  const double target = o->rtol * bnorm;
+  if (c->prec == LDG_F64 || !ctl.refine) {
+    int its;
+    double res;
+    TRY(gmres(c, c->d_G, c->d_x, target, o->restart, o->max_iters, false, &its, &res, ctl.true_res));
+    *total_its = its;
+    *sweeps_out = 0;
+    *res_out = res;
+    *ok_out = res <= target;
+    return LDG_OK;
+  }
+  TRY(dev_alloc(c, &c->d_Un, (size_t)n));
+  double* xacc = c->d_Un;  // accumulated correction
+  HIPCK(c, hipMemsetAsync(xacc, 0, sizeof(double) * n, dc.stream));
+  double* rr = c->d_R;  // refinement residual (R(U) is not needed any more)
+  HIPCK(c, hipMemcpyAsync(rr, c->d_G, sizeof(double) * n, hipMemcpyDeviceToDevice, dc.stream));
+  double rn = bnorm;
+  const int max_ref = o->max_refine > 0 ? o->max_refine : 10;
+  const double inner = o->inner_rtol > 0 ? o->inner_rtol : 1e-3;
+  int sweeps = 0, tot = 0;
+  bool ok = false;
+  for (; sweeps < max_ref; ++sweeps) {
+    int its;
+    double est;
+    TRY(gmres(c, rr, c->d_x, inner * rn, o->restart, o->max_iters - tot, false, &its, &est, false));
+    tot += its;
+    HIPCK(c, launch_axpby(xacc, 1.0, c->d_x, 1.0, n, dc.stream));
+    // exact residual rr = b - (alpha I - gamma A) xacc
+    TRY(apply_op(c, xacc, c->d_tmp, true));
+    HIPCK(c, hipMemcpyAsync(rr, c->d_G, sizeof(double) * n, hipMemcpyDeviceToDevice, dc.stream));
+    HIPCK(c, launch_axpby(rr, -1.0, c->d_tmp, 1.0, n, dc.stream));
+    TRY(norm2(c, rr, &rn));
+    if (!std::isfinite(rn)) return fail(c, LDG_E_NONFINITE, "non-finite refinement residual");
+    if (rn <= target) {
+      ++sweeps;
+      ok = true;
+      break;
+    }
+    if (tot >= o->max_iters) {
+      ++sweeps;
+      break;
+    }
+  }
+  HIPCK(c, hipMemcpyAsync(c->d_x, xacc, sizeof(double) * n, hipMemcpyDeviceToDevice, dc.stream));
+  *total_its = tot;
+  *sweeps_out = sweeps;
+  *res_out = rn;
+  *ok_out = ok;
+  return LDG_OK;
+}
+
+// One Newton iteration on G(U) = alpha (U - Ucomb) - gamma R(U).  On return
+// after an update, d_R = R(U_new) and d_G = G(U_new).
+static ldg_status newton_core(ldg_ctx c, double* U, const double* Ucomb, double alpha, double gamma,
+                              const ldg_solver_opts* o, ldg_solver_report* rep, const NewtonCtl& ctl) {
   if (!c) return LDG_E_INVALID;
   if (!U || !o) return fail(c, LDG_E_INVALID, "null pointer");
-  if (o->rtol <= 0 || o->max_iters < 1 || o->storage_prec < 0 || o->storage_prec > 2)
-    return fail(c, LDG_E_INVALID, "solver options");
+  if (!(o->rtol > 0) || o->max_iters < 1 || o->storage_prec < 0 || o->storage_prec > 2)
+    return fail(c, LDG_E_INVALID, "solver options: need rtol > 0, max_iters >= 1, storage_prec in 0..2");
+  if (!std::isfinite(alpha) || !std::isfinite(gamma)) return fail(c, LDG_E_INVALID, "alpha/gamma");
   if (o->use_learned && !c->net) return fail(c, LDG_E_INVALID, "use_learned without an attached network");
+  if ((const void*)U == (const void*)Ucomb) return fail(c, LDG_E_INVALID, "U and Ucomb alias");
   const DevCtx& dc = c->dc;
   const int64_t n = c->ndof;
   ldg_solver_report r{};
@@ -479,14 +586,12 @@ ldg_status ldg_newton_step(ldg_ctx c, double* U, const double* Ucomb, double alp
   for (auto& e : ev) HIPCK(c, hipEventCreate(&e));
   auto t_start = std::chrono::steady_clock::now();
   HIPCK(c, hipEventRecord(ev[0], dc.stream));
-  // G(U) = alpha (U - Ucomb) - gamma R(U)
-  TRY(ldg_residual(c, U, c->d_R, nullptr));
-  HIPCK(c, hipEventRecord(ev[1], dc.stream));
-  HIPCK(c, hipMemcpyAsync(c->d_G, U, sizeof(double) * n, hipMemcpyDeviceToDevice, dc.stream));
-  if (Ucomb) HIPCK(c, launch_axpby(c->d_G, -1.0, Ucomb, 1.0, n, dc.stream));
-  HIPCK(c, launch_axpby(c->d_G, -gamma, c->d_R, alpha, n, dc.stream));
   double g0;
-  TRY(norm2(c, c->d_G, &g0));
+  if (ctl.G_current)
+    TRY(norm2(c, c->d_G, &g0));
+  else
+    TRY(eval_G(c, U, Ucomb, alpha, gamma, c->d_G, &g0));
+  HIPCK(c, hipEventRecord(ev[1], dc.stream));
   r.newton_res_before = g0;
   if (!std::isfinite(g0)) return fail(c, LDG_E_NONFINITE, "non-finite Newton residual");
   const bool reassemble = o->reassemble || !c->assembled || c->alpha != alpha || c->gamma != gamma ||
@@ -494,73 +599,57 @@ ldg_status ldg_newton_step(ldg_ctx c, double* U, const double* Ucomb, double alp
   if (reassemble) {
     c->learned_enabled = c->net && o->use_learned;
     TRY(assemble(c, U, alpha, gamma, o->storage_prec, c->d_R));
+    c->n_assemblies++;
   }
   r.fallback_used = c->learned_fallback;
   HIPCK(c, hipEventRecord(ev[2], dc.stream));
-  // b = -G  (kept in d_G)
+  // b = -G  (kept in d_G during the solve)
   HIPCK(c, launch_axpby(c->d_G, 0.0, c->d_G, -1.0, n, dc.stream));
-  const double target = o->rtol * g0;
-  int total_its = 0;
+  int its = 0, sweeps = 0;
   double res = 0.0;
   bool ok = false;
-  if (c->prec == LDG_F64) {
-    int its;
-    TRY(gmres(c, c->d_G, c->d_x, target, o->restart, o->max_iters, false, &its, &res));
-    total_its = its;
-    ok = res <= target;
-    r.refine_steps = 0;
-  } else {
-    // FP64 iterative refinement around the low-precision GMRES
-    TRY(dev_alloc(c, &c->d_Un, (size_t)n));
-    double* xacc = c->d_Un;  // accumulated correction
-    HIPCK(c, hipMemsetAsync(xacc, 0, sizeof(double) * n, dc.stream));
-    std::vector<double> dummy;
-    double* rr = c->d_R;  // reuse R buffer for the refinement residual
-    HIPCK(c, hipMemcpyAsync(rr, c->d_G, sizeof(double) * n, hipMemcpyDeviceToDevice, dc.stream));
-    double rn = g0;
-    const int max_ref = o->max_refine > 0 ? o->max_refine : 10;
-    const double inner = o->inner_rtol > 0 ? o->inner_rtol : 1e-3;
-    int sweeps = 0;
-    for (; sweeps < max_ref; ++sweeps) {
-      int its;
-      double est;
-      TRY(gmres(c, rr, c->d_x, inner * rn, o->restart, o->max_iters - total_its, false, &its, &est, false));
-      total_its += its;
-      HIPCK(c, launch_axpby(xacc, 1.0, c->d_x, 1.0, n, dc.stream));
-      // exact residual rr = b - (alpha I - gamma A) xacc
-      TRY(apply_op(c, xacc, c->d_tmp, true));
-      HIPCK(c, hipMemcpyAsync(rr, c->d_G, sizeof(double) * n, hipMemcpyDeviceToDevice, dc.stream));
-      HIPCK(c, launch_axpby(rr, -1.0, c->d_tmp, 1.0, n, dc.stream));
-      TRY(norm2(c, rr, &rn));
-      if (!std::isfinite(rn)) return fail(c, LDG_E_NONFINITE, "non-finite refinement residual");
-      if (rn <= target) {
-        ++sweeps;
-        ok = true;
-        break;
-      }
-      if (total_its >= o->max_iters) {
-        ++sweeps;
-        break;
-      }
-    }
-    r.refine_steps = sweeps;
-    res = rn;
-    HIPCK(c, hipMemcpyAsync(c->d_x, xacc, sizeof(double) * n, hipMemcpyDeviceToDevice, dc.stream));
+  TRY(linear_solve(c, o, ctl, g0, &its, &sweeps, &res, &ok));
+  r.gmres_iters = its;
+  // the learned correction is judged by the outcome: a solve that misses the
+  // tolerance is repeated with the plain BILU(0) factors
+  if (!ok && c->learned_active) {
+    c->learned_active = false;
+    c->learned_fallback = 1;
+    r.fallback_used = 1;
+    TRY(linear_solve(c, o, ctl, g0, &its, &sweeps, &res, &ok));
+    r.gmres_iters += its;
   }
   HIPCK(c, hipEventRecord(ev[3], dc.stream));
-  r.gmres_iters = total_its;
+  r.refine_steps = sweeps;
   r.lin_relres = g0 > 0 ? res / g0 : 0.0;
   r.converged = ok ? 1 : 0;
-  if (ok) {
+  const bool update = ok || ctl.accept_inexact;
+  if (update) {
+    TRY(dev_alloc(c, &c->d_Uold, (size_t)n));
+    HIPCK(c, launch_copy(c->d_Uold, U, n, dc.stream));
     HIPCK(c, launch_axpby(U, 1.0, c->d_x, 1.0, n, dc.stream));
-    // ||G(U_new)||
-    TRY(ldg_residual(c, U, c->d_R, nullptr));
-    HIPCK(c, hipMemcpyAsync(c->d_tmp, U, sizeof(double) * n, hipMemcpyDeviceToDevice, dc.stream));
-    if (Ucomb) HIPCK(c, launch_axpby(c->d_tmp, -1.0, Ucomb, 1.0, n, dc.stream));
-    HIPCK(c, launch_axpby(c->d_tmp, -gamma, c->d_R, alpha, n, dc.stream));
     double g1;
-    TRY(norm2(c, c->d_tmp, &g1));
+    TRY(eval_G(c, U, Ucomb, alpha, gamma, c->d_tmp, &g1));
+    if (c->learned_active && !(g1 < g0)) {
+      // the corrected step did not lower ||G||: undo it and solve again with plain BILU(0)
+      c->learned_active = false;
+      c->learned_fallback = 1;
+      r.fallback_used = 1;
+      HIPCK(c, launch_copy(U, c->d_Uold, n, dc.stream));
+      TRY(linear_solve(c, o, ctl, g0, &its, &sweeps, &res, &ok));
+      r.gmres_iters += its;
+      r.refine_steps = sweeps;
+      r.lin_relres = g0 > 0 ? res / g0 : 0.0;
+      r.converged = ok ? 1 : 0;
+      if (ok || ctl.accept_inexact) {
+        HIPCK(c, launch_axpby(U, 1.0, c->d_x, 1.0, n, dc.stream));
+        TRY(eval_G(c, U, Ucomb, alpha, gamma, c->d_tmp, &g1));
+      } else {
+        g1 = g0;
+      }
+    }
     r.newton_res_after = g1;
+    HIPCK(c, launch_copy(c->d_G, c->d_tmp, n, dc.stream));
   } else {
     r.newton_res_after = g0;
   }
@@ -588,7 +677,151 @@ ldg_status ldg_newton_step(ldg_ctx c, double* U, const double* Ucomb, double alp
   c->timing = false;
   for (auto& e : ev) hipEventDestroy(e);
   if (rep) *rep = r;
-  if (!ok) return fail(c, LDG_E_NOT_CONVERGED, "linear solve did not reach rtol");
+  if (!update) return fail(c, LDG_E_NOT_CONVERGED, "linear solve did not reach rtol");
+  return LDG_OK;
+}
+
+ldg_status ldg_newton_step(ldg_ctx c, double* U, const double* Ucomb, double alpha, double gamma,
+                           const ldg_solver_opts* o, ldg_solver_report* rep) {
+  return newton_core(c, U, Ucomb, alpha, gamma, o, rep, NewtonCtl{});
+}
+
+// ------------------------------------------------------------------ implicit time steps
+// Alexander's L-stable three-stage DIRK (Section 4.1): diagonal alpha, c_2 = tau_2.
+static const double kDirkAlpha = 0.435866521508459;
+
+ldg_status ldg_implicit_step(ldg_ctx c, double* U, double* Uprev, double dt, const ldg_step_opts* so,
+                             const ldg_solver_opts* lo, ldg_step_report* rep) {
+  if (!c) return LDG_E_INVALID;
+  if (!U || !so || !lo) return fail(c, LDG_E_INVALID, "null pointer");
+  if (so->scheme < LDG_BDF2 || so->scheme > LDG_BACKWARD_EULER) return fail(c, LDG_E_INVALID, "scheme");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(c, LDG_E_INVALID, "dt must be positive and finite");
+  if (so->max_newton < 1) return fail(c, LDG_E_INVALID, "max_newton must be >= 1");
+  if (!(so->newton_rtol >= 0) || !(so->newton_atol >= 0))
+    return fail(c, LDG_E_INVALID, "need newton_rtol >= 0 and newton_atol >= 0");
+  const bool fixed = so->newton_rtol == 0 && so->newton_atol == 0;  // exactly max_newton iterations
+  if (so->gmres_per_newton < 0) return fail(c, LDG_E_INVALID, "gmres_per_newton must be >= 0");
+  if ((const void*)U == (const void*)Uprev) return fail(c, LDG_E_INVALID, "U and Uprev alias");
+  const DevCtx& dc = c->dc;
+  const int64_t n = c->ndof;
+  auto t_start = std::chrono::steady_clock::now();
+  TRY(dev_alloc(c, &c->d_st_Un, (size_t)n));
+  TRY(dev_alloc(c, &c->d_st_comb, (size_t)n));
+  TRY(dev_alloc(c, &c->d_st_K, (size_t)2 * n));
+  double* Un = c->d_st_Un;
+  double* comb = c->d_st_comb;
+  double* dK1 = c->d_st_K;  // dt K_1 (DIRK)
+  double* dK2 = c->d_st_K + n;
+  HIPCK(c, launch_copy(Un, U, n, dc.stream));
+  ldg_step_report r{};
+  // linear solves: a fixed number of GMRES iterations per Newton iteration
+  // (the stored operator, no refinement: the FP64 Newton residual corrects
+  // it), or GMRES to lo->rtol as in ldg_newton_step
+  ldg_solver_opts lin = *lo;
+  NewtonCtl ctl;
+  ctl.accept_inexact = true;
+  if (so->gmres_per_newton > 0) {
+    lin.max_iters = so->gmres_per_newton;
+    lin.restart = lo->restart > so->gmres_per_newton ? so->gmres_per_newton : lo->restart;
+    ctl.refine = false;
+    ctl.true_res = false;
+  }
+  const int nstage = so->scheme == LDG_DIRK3 ? 3 : 1;
+  double gamma;
+  if (so->scheme == LDG_BDF2)
+    gamma = 2.0 * dt / 3.0;
+  else if (so->scheme == LDG_BACKWARD_EULER)
+    gamma = dt;
+  else
+    gamma = kDirkAlpha * dt;
+  const double a = kDirkAlpha, tau2 = 0.5 * (1.0 + a);
+  const double b1 = -(6 * a * a - 16 * a + 1) / 4, b2 = (6 * a * a - 20 * a + 5) / 4;
+  const int n_asm0 = c->n_assemblies;
+  bool all_ok = true;
+  for (int st = 0; st < nstage && all_ok; ++st) {
+    // Ucomb of the stage: the explicit part of the stage equation
+    if (so->scheme == LDG_BDF2) {
+      // (4 U^n - U^{n-1}) / 3, with U^{n-1} = U^n when no history is given
+      HIPCK(c, launch_copy(comb, Un, n, dc.stream));
+      if (Uprev) {
+        HIPCK(c, launch_axpby(comb, -1.0 / 3.0, Uprev, 4.0 / 3.0, n, dc.stream));
+      }
+    } else if (so->scheme == LDG_BACKWARD_EULER || st == 0) {
+      HIPCK(c, launch_copy(comb, Un, n, dc.stream));
+    } else if (st == 1) {
+      HIPCK(c, launch_copy(comb, Un, n, dc.stream));
+      HIPCK(c, launch_axpby(comb, tau2 - a, dK1, 1.0, n, dc.stream));
+    } else {
+      HIPCK(c, launch_copy(comb, Un, n, dc.stream));
+      HIPCK(c, launch_axpby(comb, b1, dK1, 1.0, n, dc.stream));
+      HIPCK(c, launch_axpby(comb, b2, dK2, 1.0, n, dc.stream));
+    }
+    // Newton iterations on Y - Ucomb - gamma F(Y) = 0 starting from the current U
+    double g_first = 0.0, g = 0.0;
+    TRY(eval_G(c, U, comb, 1.0, gamma, c->d_G, &g_first));
+    if (!std::isfinite(g_first)) {
+      c->err = "non-finite residual at the start of stage " + std::to_string(st + 1);
+      all_ok = false;
+      break;
+    }
+    g = g_first;
+    const double tol = std::max(so->newton_rtol * g_first, so->newton_atol);
+    int k = 0, since = 0;
+    bool conv = !fixed && g <= tol;
+    while (!conv && k < so->max_newton) {
+      lin.reassemble = (!so->reuse) || (so->reassemble_after > 0 && since >= so->reassemble_after) ? 1 : 0;
+      if (lin.reassemble) since = 0;
+      ldg_solver_report nr{};
+      ctl.G_current = true;
+      ldg_status s = newton_core(c, U, comb, 1.0, gamma, &lin, &nr, ctl);
+      if (s != LDG_OK) {
+        all_ok = false;
+        break;
+      }
+      ++k;
+      ++since;
+      r.gmres_iters += nr.gmres_iters;
+      r.fallback_used |= nr.fallback_used;
+      r.lin_relres_max = std::max(r.lin_relres_max, nr.lin_relres);
+      r.t_assemble_ms += nr.t_assemble_ms;
+      r.t_solve_ms += nr.t_solve_ms;
+      g = nr.newton_res_after;
+      if (!std::isfinite(g)) {
+        c->err = "non-finite Newton residual in stage " + std::to_string(st + 1);
+        all_ok = false;
+        break;
+      }
+      conv = fixed ? k >= so->max_newton : g <= tol;
+    }
+    r.newton_iters += k;
+    if (k > r.max_stage_newton) r.max_stage_newton = k;
+    if (st == 0) r.newton_res_first = g_first;
+    r.newton_res_final = g;
+    ++r.stages;
+    if (all_ok && !conv) {
+      c->err = "stage " + std::to_string(st + 1) + ": ||G|| = " + std::to_string(g) + " after " +
+               std::to_string(k) + " Newton iterations, tolerance " + std::to_string(tol);
+      all_ok = false;
+      break;
+    }
+    if (so->scheme == LDG_DIRK3 && st < 2) {
+      // dt K_i = (Y_i - Ucomb_i) / alpha
+      double* dK = st == 0 ? dK1 : dK2;
+      HIPCK(c, launch_copy(dK, U, n, dc.stream));
+      HIPCK(c, launch_axpby(dK, -1.0 / a, comb, 1.0 / a, n, dc.stream));
+    }
+  }
+  r.assemblies = c->n_assemblies - n_asm0;
+  r.converged = all_ok ? 1 : 0;
+  if (all_ok) {
+    if (so->scheme == LDG_BDF2 && Uprev) HIPCK(c, launch_copy(Uprev, Un, n, dc.stream));
+  } else {
+    HIPCK(c, launch_copy(U, Un, n, dc.stream));  // U unchanged on failure
+  }
+  HIPCK(c, hipStreamSynchronize(dc.stream));
+  r.t_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  if (rep) *rep = r;
+  if (!all_ok) return LDG_E_NOT_CONVERGED;
   return LDG_OK;
 }
 

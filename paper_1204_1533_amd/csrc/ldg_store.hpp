@@ -7,13 +7,23 @@ namespace ldg {
 
 constexpr int PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2;
 
-// float -> bfloat16, round to nearest even (finite inputs)
-__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
-  uint32_t b = __float_as_uint(f);
+// float -> bfloat16, round to nearest even.  A NaN stays a (quiet) NaN: adding
+// the rounding increment to its bits could carry into the sign or turn it into
+// an infinity, so its upper half is kept with the quiet bit set instead.
+// Finite values that round past the largest bfloat16 become infinities.
+__host__ __device__ inline uint16_t f32_to_bf16(float f) {
+  uint32_t b;
+  __builtin_memcpy(&b, &f, sizeof(b));
+  if ((b & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((b >> 16) | 0x0040u);
   b += 0x7FFFu + ((b >> 16) & 1u);
   return (uint16_t)(b >> 16);
 }
-__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+__host__ __device__ inline float bf16_to_f32(uint16_t h) {
+  const uint32_t b = ((uint32_t)h) << 16;
+  float f;
+  __builtin_memcpy(&f, &b, sizeof(f));
+  return f;
+}
 
 template <int PREC> struct Store;
 template <> struct Store<PREC_F64> {

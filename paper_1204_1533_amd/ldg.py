@@ -56,6 +56,30 @@ class ldg_solver_report(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+LDG_BDF2, LDG_DIRK3, LDG_BACKWARD_EULER = 0, 1, 2
+
+
+class ldg_step_opts(ctypes.Structure):
+    _fields_ = [
+        ("scheme", ctypes.c_int32), ("max_newton", ctypes.c_int32), ("newton_rtol", ctypes.c_double),
+        ("newton_atol", ctypes.c_double), ("gmres_per_newton", ctypes.c_int32), ("reuse", ctypes.c_int32),
+        ("reassemble_after", ctypes.c_int32),
+    ]
+
+
+class ldg_step_report(ctypes.Structure):
+    _fields_ = [
+        ("stages", ctypes.c_int32), ("newton_iters", ctypes.c_int32), ("max_stage_newton", ctypes.c_int32),
+        ("assemblies", ctypes.c_int32), ("gmres_iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+        ("fallback_used", ctypes.c_int32), ("newton_res_first", ctypes.c_double),
+        ("newton_res_final", ctypes.c_double), ("lin_relres_max", ctypes.c_double),
+        ("t_assemble_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double), ("t_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class ldg_sample_batch(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("n_probe", ctypes.c_int32), ("X_dev", ctypes.c_void_p),
                 ("A_dev", ctypes.c_void_p), ("S_dev", ctypes.c_void_p), ("T_dev", ctypes.c_void_p)]
@@ -75,6 +99,8 @@ _SIGS = {
     "ldg_export_operators": (ctypes.c_int, [_P, _P, _P, _P]),
     "ldg_newton_step": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.c_double,
                                        ctypes.POINTER(ldg_solver_opts), ctypes.POINTER(ldg_solver_report)]),
+    "ldg_implicit_step": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.POINTER(ldg_step_opts),
+                                         ctypes.POINTER(ldg_solver_opts), ctypes.POINTER(ldg_step_report)]),
     "ldg_rk4": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int32]),
     "ldg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "ldg_last_error": (ctypes.c_char_p, [_P]),
@@ -160,7 +186,7 @@ class Context:
         h = _P()
         st = lib.ldg_create(ctypes.byref(d), stream, ctypes.byref(h))
         if st != LDG_OK:
-            raise LDGError(st, lib.ldg_status_string(st).decode())
+            raise LDGError(st, lib.ldg_last_error(None).decode())
         self.h = h
         self.dim, self.p = mesh.dim, mesh.p
         self.m = 1 if equation == LDG_POISSON else mesh.dim + 2
@@ -215,6 +241,21 @@ class Context:
         rep = ldg_solver_report()
         st = self.lib.ldg_newton_step(self.h, _ptr(U), _ptr(Ucomb), float(alpha), float(gamma), ctypes.byref(o),
                                       ctypes.byref(rep))
+        if raise_on_error:
+            self._check(st)
+        out = rep.as_dict()
+        out["status"] = st
+        return out
+
+    def ldg_implicit_step(self, U, Uprev, dt, scheme=LDG_DIRK3, max_newton=30, newton_rtol=1e-8, newton_atol=0.0,
+                          gmres_per_newton=0, reuse=1, reassemble_after=15, restart=50, max_iters=2000,
+                          max_refine=20, storage_prec=LDG_F64, rtol=1e-8, inner_rtol=1e-3, use_learned=0,
+                          raise_on_error=True):
+        so = ldg_step_opts(scheme, max_newton, newton_rtol, newton_atol, gmres_per_newton, reuse, reassemble_after)
+        lo = ldg_solver_opts(restart, max_iters, max_refine, storage_prec, rtol, inner_rtol, use_learned, 0)
+        rep = ldg_step_report()
+        st = self.lib.ldg_implicit_step(self.h, _ptr(U), _ptr(Uprev), float(dt), ctypes.byref(so), ctypes.byref(lo),
+                                        ctypes.byref(rep))
         if raise_on_error:
             self._check(st)
         out = rep.as_dict()

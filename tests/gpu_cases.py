@@ -48,7 +48,45 @@ def small_poisson_3d(p=2, n=2):
                            gD=fields.face_values(mesh, u), c11_dirichlet=10.0)
 
 
+def flip_mesh(mesh, seed, frac=0.5):
+    """Reverse two local axes of a seeded random subset of elements (a rotation by 180 degrees
+    in the plane of those axes) and renumber the elements, so that switch signs S = -1 and
+    reversed face-node maps occur.  Returns (mesh, flips, perm)."""
+    from ldg_workloads import reorient_elements
+    rng = np.random.default_rng(seed)
+    E, D = mesh.n_elem, mesh.dim
+    flips = np.zeros((E, D), dtype=bool)
+    for e in np.nonzero(rng.random(E) < frac)[0]:
+        flips[e, rng.choice(D, size=2, replace=False)] = True
+    perm = rng.permutation(E)
+    return reorient_elements(mesh, flips, perm), flips, perm
+
+
+def relabel_nodal(V, mesh, flips, perm):
+    """A nodal field [E][C][Np] of the original mesh in the numbering of the flipped mesh."""
+    n1, D = mesh.p + 1, mesh.dim
+    idx = np.arange(mesh.np_)
+    coords = [(idx // n1 ** d) % n1 for d in range(D)]
+    out = np.empty_like(V)
+    for e in range(mesh.n_elem):
+        old = np.zeros_like(idx)
+        for d in reversed(range(D)):
+            c = mesh.p - coords[d] if flips[e, d] else coords[d]
+            old = old * n1 + c
+        out[perm[e]] = V[e][:, old]
+    return out
+
+
 def case(name):
+    if name.endswith("_flip"):
+        # the same workload on a mesh whose elements have reversed axes (S = -1 faces)
+        pr = case(name[:-len("_flip")])
+        assert pr.source is None and pr.gD is None
+        mesh2, flips, perm = flip_mesh(pr.mesh, seed=17)
+        U2 = relabel_nodal(pr.U0, pr.mesh, flips, perm)
+        return configs.Problem(pr.name + "_flip", mesh2, pr.equation, pr.m, U2, gamma=pr.gamma, mu=pr.mu,
+                               prandtl=pr.prandtl, c11_interior=pr.c11_interior,
+                               c11_dirichlet=pr.c11_dirichlet, dt=pr.dt, extra=dict(pr.extra))
     if name == "C1":
         pr = configs.config1()
         pr.U0 = pr.extra["u_exact"] + 0.01 * np.sin(7 * pr.mesh.xyz[:, 0:1])  # a non-trivial state
@@ -71,17 +109,31 @@ def case(name):
     raise KeyError(name)
 
 
-def rounding_sensitivity(orc, pr, elems=None, seed=0):
+def rounding_sensitivity(orc, pr, elems=None, seed=0, per_component=False):
     """Largest change of the oracle residual under random one-ulp perturbations of its
     inputs (node coordinates, then state): the scale of rounding differences that two
-    correct FP64 evaluations of the same residual can show."""
+    correct FP64 evaluations of the same residual can show (per component if asked)."""
     from oracle import LineDG
     rng = np.random.default_rng(seed)
     base = orc.residual(pr.U0, elems=elems)
     x = pr.mesh.xyz * (1 + 2.0 ** -52 * rng.standard_normal(pr.mesh.xyz.shape))
     o2 = LineDG(pr.mesh.dim, pr.mesh.p, x, pr.mesh.face_nbr, pr.mesh.nbr_node, pr.mesh.switch_plus, orc.ph,
                 pr.c11_interior, pr.c11_dirichlet, pr.source, pr.gD)
-    s1 = float((o2.residual(pr.U0, elems=elems) - base).abs().max())
+    d1 = (o2.residual(pr.U0, elems=elems) - base).abs()
     U1 = pr.U0 * (1 + 2.0 ** -52 * rng.standard_normal(pr.U0.shape))
-    s2 = float((orc.residual(U1, elems=elems) - base).abs().max())
-    return max(s1, s2)
+    d2 = (orc.residual(U1, elems=elems) - base).abs()
+    if per_component:
+        return np.maximum(d1.amax(dim=(0, 2)).numpy(), d2.amax(dim=(0, 2)).numpy())
+    return max(float(d1.max()), float(d2.max()))
+
+
+def record(case_name, quantity, err, bound):
+    """Append a measured parity error and its bound to the file named by LDG_PARITY_LOG (if set)."""
+    import json
+    import os
+    path = os.environ.get("LDG_PARITY_LOG")
+    print(f"  [{case_name}] {quantity}: error {err:.3e}, bound {bound:.3e}, ratio {err / bound if bound else 0:.2e}",
+          flush=True)
+    if path:
+        with open(path, "a") as f:
+            f.write(json.dumps({"case": case_name, "quantity": quantity, "err": float(err), "bound": float(bound)}) + "\n")

@@ -64,6 +64,7 @@ def test_create_rejects_bad_descriptions(lib):
     mesh = quad_mesh(3, 3, 2, periodic=(True, True))
     d, keep = _desc(mesh, p=7)
     assert _create(lib, d) == ldg.LDG_E_UNSUPPORTED
+    assert lib.ldg_last_error(None) == b"ldg_create: p must be in 1..4"
     d, keep = _desc(mesh, dim=4)
     assert _create(lib, d) == ldg.LDG_E_UNSUPPORTED
     d, keep = _desc(mesh, gamma=0.5)
@@ -77,6 +78,7 @@ def test_create_rejects_bad_descriptions(lib):
     mesh2 = type(mesh)(mesh.dim, mesh.p, mesh.xyz, mesh.face_nbr, bad, mesh.switch_plus)
     d, keep = _desc(mesh2)
     assert _create(lib, d) == ldg.LDG_E_SHAPE
+    assert b"not reciprocal" in lib.ldg_last_error(None)
     # switch signs not opposite across a face
     sw = mesh.switch_plus.copy()
     sw[4, 0] = -1
@@ -89,6 +91,7 @@ def test_create_rejects_bad_descriptions(lib):
     mesh4 = type(mesh)(mesh.dim, mesh.p, mesh.xyz, mesh.face_nbr, mesh.nbr_node, sw)
     d, keep = _desc(mesh4)
     assert _create(lib, d) == ldg.LDG_E_INVALID
+    assert b"switch_plus must be +-1 (element 0)" in lib.ldg_last_error(None)
     # Dirichlet faces need a positive penalty (Poisson)
     m5 = quad_mesh(2, 2, 2)
     d, keep = _desc(m5, equation=0, c11_dirichlet=0.0)
@@ -120,3 +123,13 @@ def test_learned_entry_points_validate_before_device_work(lib):
     el = (ctypes.c_int64 * 1)(0)
     assert lib.ldg_learned_samples(None, el, 1, None, 1, None, None, None, None) == ldg.LDG_E_INVALID
     lib.ldg_net_destroy(None)
+
+
+def test_time_step_and_newton_validate_before_device_work(lib):
+    from paper_1204_1533_amd import ldg
+    so = ldg.ldg_step_opts(ldg.LDG_DIRK3, 10, 1e-8, 0.0, 0, 1, 15)
+    lo = ldg.ldg_solver_opts(50, 100, 10, 0, 1e-8, 1e-3, 0, 0)
+    rep = ldg.ldg_step_report()
+    assert lib.ldg_implicit_step(None, None, None, 0.1, ctypes.byref(so), ctypes.byref(lo),
+                                 ctypes.byref(rep)) == ldg.LDG_E_INVALID
+    assert lib.ldg_newton_step(None, None, None, 1.0, 0.1, ctypes.byref(lo), None) == ldg.LDG_E_INVALID

@@ -296,6 +296,38 @@ def test_zero_output_and_nonfinite_fallback():
     net.close()
 
 
+def test_harmful_correction_is_rejected_by_the_outcome():
+    """A finite but harmful correction (a large constant output bias) makes the corrected solve
+    miss the tolerance within the iterations that plain BILU(0) needs; the Newton step then
+    repeats the solve with the plain factors, reports the fallback, and gives the plain result."""
+    print("[gpu] learned harmful correction fallback", flush=True)
+    pr = case("tgv2p3")
+    gamma = 0.03
+    U = torch.as_tensor(pr.U0, device="cuda").contiguous()
+    ref = gpu_of(pr)
+    U_ref = U.clone()
+    rep0 = ref.ldg_newton_step(U_ref, U, 1.0, gamma, storage_prec=1, max_iters=600, rtol=1e-8)
+    n_plain = rep0["gmres_iters"]
+    net = Net(3, 3, 5, hidden=64, seed=3, stream=stream())
+    w = torch.zeros(net.ldg_net_num_params(), device="cuda")
+    w[-net.n_out:] = 50.0
+    net.ldg_net_set_params(w)
+    ctx = gpu_of(pr)
+    ctx.ldg_learned_attach(net, LDG_F32)
+    U_l = U.clone()
+    rep = ctx.ldg_newton_step(U_l, U, 1.0, gamma, storage_prec=1, use_learned=1, max_iters=n_plain, rtol=1e-8)
+    torch.cuda.synchronize()
+    print(f"  plain {n_plain} iterations; with the harmful correction: {rep}", flush=True)
+    assert rep["fallback_used"] == 1 and rep["converged"] == 1
+    assert rep["lin_relres"] <= 1e-8
+    err = float((U_l - U_ref).abs().max())
+    assert err <= 1e-12 * float((U_ref - U).abs().max())
+    assert ctx.ldg_learned_active() == 0
+    ctx.close()
+    ref.close()
+    net.close()
+
+
 # ------------------------------------------------------------------ what the trained network gains
 def test_learned_gain_over_ilu0():
     """Train on solver-generated samples (12^3, p = 3 Navier-Stokes runs, seeds 0-7), then compare

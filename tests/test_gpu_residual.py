@@ -1,17 +1,24 @@
 """GPU residual and LDG gradient against the FP64 oracle (through the C ABI).
 
-Tolerance (FP64 residual), normwise:
-    max |R_gpu - R_orc| <= max(1e-12 * max(|R_orc|_inf, |R_abs|_inf), 4 S)
-where S is the oracle's own response to random one-ulp perturbations of its
-inputs (node coordinates and state) on the same elements, and R_abs = (1/J) sum_n |r^(n)| + |S| is the oracle's magnitude of the
-terms summed into R.  The residual differentiates the node coordinates, and
-its response to a one-ulp perturbation of them is of the same size as the
-GPU/oracle difference (about 5e-13 |R_abs|_inf on the perturbed p = 4 vortex
-mesh), so the bound is relative to the summed terms rather than to R itself,
-which cancels them.  Q = K21 U + (boundary data) is linear in U; its bound is
-the forward-error scale of a linear operator,
-    max |Q_gpu - Q_orc| <= 1e-12 * max(|Q_orc|_inf, |U|_inf * ||K21||_inf),
-with ||K21||_inf the largest absolute row sum of the oracle's gradient weights.
+Tolerance of the FP64 residual, per solution component c:
+    max |R_gpu - R_orc|[c] <= max(1e-12 * max(|R_orc[c]|_inf, |R_abs[c]|_inf), 4 S[c])
+with R_abs = (1/J) sum_n |r^(n)| + |S| the oracle's magnitude of the terms summed
+into R.  R cancels these terms (a near-steady or freestream state has R ~ 0
+with terms of size R_abs), so two correct FP64 evaluations agree relative to
+R_abs, not to R.  S[c] is the oracle's own change under random one-ulp
+perturbations of its inputs (node coordinates and state); it is only needed on
+the curved 3-D p = 4 mesh, where the residual differentiates the coordinates
+and a one-ulp perturbation moves R by about 2e-12 R_abs; elsewhere the 1e-12
+term is the active one.  Components are judged separately so that the small
+ones (density, momentum) are not measured against the energy's scale.
+
+Tolerance of Q = K21 U + (boundary data), entry by entry: the forward-error
+scale of the linear operator,
+    |Q_gpu - Q_orc| <= 1e-12 * (|K21| |U| + |Q_orc - K21 U|),
+with |K21| |U| the sum over the stencil of |weight| |value| (the oracle's K21
+weights) and the last term the inhomogeneous (Dirichlet) part.  Q cancels
+these sums strongly (|K21||U| / |Q| is about 4e3 for the energy on the 16^3
+workload), which is why the bound is per entry and relative to them.
 """
 import sys
 
@@ -19,12 +26,13 @@ import numpy as np
 import pytest
 import torch
 
-from tests.gpu_cases import case, gpu_of, oracle_of, rounding_sensitivity
+from tests.gpu_cases import case, gpu_of, oracle_of, record, rounding_sensitivity
 
 pytestmark = pytest.mark.gpu
 
 FULL = ["C1", "C2", "ns2d_p1", "ns2d_p2", "ns2d_p3", "ns2d_p4", "euler3d_p1", "euler3d_p2", "euler3d_p3",
-        "euler3d_p4", "poisson3d_p2", "poisson3d_p3", "tgv3p2", "tgv2p4"]
+        "euler3d_p4", "poisson3d_p2", "poisson3d_p3", "tgv3p2", "tgv2p4", "ns2d_p3_flip", "ns2d_p4_flip",
+        "euler3d_p3_flip", "tgv2p3_flip", "tgv2p4_flip"]
 
 
 def run_gpu(pr, want_q=True):
@@ -37,23 +45,35 @@ def run_gpu(pr, want_q=True):
     return ctx, U, R.cpu().numpy(), Q.cpu().numpy()
 
 
-def check_R(R_gpu, R_orc, mag, sens=0.0):
+def check_R(name, R_gpu, R_orc, mag, sens=None):
     R_orc = R_orc.numpy()
-    scale = max(np.abs(R_orc).max(), mag.numpy().max())
-    bound = max(1e-12 * scale, 4.0 * sens)
-    err = np.abs(R_gpu - R_orc).max()
-    print(f"  max|R_gpu - R_orc| = {err:.3e}, bound {bound:.3e} (1e-12 scale {1e-12 * scale:.3e}, "
-          f"ulp sensitivity {sens:.3e})", flush=True)
-    assert err <= bound, (err, bound)
+    mag = mag.numpy()
+    for c in range(R_orc.shape[1]):
+        err = np.abs(R_gpu[:, c] - R_orc[:, c]).max()
+        b12 = 1e-12 * max(np.abs(R_orc[:, c]).max(), mag[:, c].max())
+        bound = b12 if sens is None else max(b12, 4.0 * sens[c])
+        record(name, f"R[{c}] (1e-12 term {b12:.2e})", err, bound)
+        assert err <= bound, (c, err, bound)
 
 
-def check_Q(Q_gpu, Q_orc, orc, U, elems):
-    W = orc.k21(elems).numpy()
-    k21_norm = np.abs(W).sum(axis=2).max()
-    scale = max(np.abs(Q_orc).max(), np.abs(U).max() * k21_norm)
-    err = np.abs(Q_gpu - Q_orc).max()
-    print(f"  max|Q_gpu - Q_orc| = {err:.3e}, bound {1e-12 * scale:.3e}", flush=True)
-    assert err <= 1e-12 * scale
+def check_Q(name, Q_gpu, Q_orc, orc, U, elems):
+    """Entrywise forward-error bound of the linear gradient operator."""
+    import torch as T
+    W = orc.k21(elems)  # [Ne, Np, ns, D]
+    cols = orc.column_nodes("K21")[np.asarray(elems if elems is not None else np.arange(orc.E))]
+    E, m, Np = orc.E, orc.m, orc.Np
+    Uf = T.as_tensor(U).reshape(E, m, Np).permute(0, 2, 1).reshape(E * Np, m)
+    c = T.as_tensor(cols)
+    ok = c >= 0
+    xs = Uf[T.where(ok, c, T.zeros_like(c))] * ok[..., None].to(T.float64)  # [Ne, Np, ns, m]
+    absWU = T.einsum("easd,easc->ecda", W.abs(), xs.abs()).numpy()
+    WU = T.einsum("easd,easc->ecda", W, xs).numpy()
+    scale = absWU + np.abs(Q_orc - WU)
+    ratio = np.abs(Q_gpu - Q_orc) / np.maximum(scale, 1e-300)
+    err = float(np.abs(Q_gpu - Q_orc).max())
+    worst = float(ratio.max())
+    record(name, f"Q entrywise (max abs err {err:.2e})", worst * 1e-12, 1e-12)
+    assert worst <= 1e-12, worst
 
 
 @pytest.mark.parametrize("name", FULL)
@@ -63,9 +83,12 @@ def test_residual_parity_full(name):
     ctx, U, R_gpu, Q_gpu = run_gpu(pr)
     orc = oracle_of(pr)
     R_orc, mag = orc.residual(pr.U0, return_abs=True)
-    check_R(R_gpu, R_orc, mag)
+    sens = None
+    if pr.mesh.dim == 3 and pr.mesh.p == 4 and pr.equation == 2:
+        sens = rounding_sensitivity(orc, pr, per_component=True)
+    check_R(name, R_gpu, R_orc, mag, sens)
     if pr.equation != 1:
-        check_Q(Q_gpu, orc.gradient(pr.U0).numpy(), orc, pr.U0, None)
+        check_Q(name, Q_gpu, orc.gradient(pr.U0).numpy(), orc, pr.U0, None)
     ctx.close()
 
 
@@ -80,8 +103,13 @@ def test_residual_parity_sampled(name):
     sample = np.unique(np.concatenate([[0, E - 1], rng.choice(E, size=24, replace=False)]))
     orc = oracle_of(pr)
     R_orc, mag = orc.residual(pr.U0, elems=sample, return_abs=True)
-    check_R(R_gpu[sample], R_orc, mag, rounding_sensitivity(orc, pr, sample))
-    check_Q(Q_gpu[sample], orc.gradient(pr.U0, elems=sample).numpy(), orc, pr.U0, sample)
+    sens = rounding_sensitivity(orc, pr, sample, per_component=True) if pr.mesh.p == 4 else None
+    check_R(name, R_gpu[sample], R_orc, mag, sens)
+    Rn = R_orc.numpy()
+    err = np.abs(R_gpu[sample] - Rn)
+    print(f"  {name}: max|R_gpu - R_orc| = {err.max():.3e}; relative to |R|_inf {err.max() / np.abs(Rn).max():.3e}, "
+          f"to |R_abs|_inf {err.max() / mag.numpy().max():.3e}", flush=True)
+    check_Q(name, Q_gpu[sample], orc.gradient(pr.U0, elems=sample).numpy(), orc, pr.U0, sample)
     # properties that hold at any size: finite, and repeatable bit for bit
     assert np.all(np.isfinite(R_gpu))
     R2 = torch.empty_like(U)
@@ -107,8 +135,9 @@ def test_freestream_and_conservation_gpu():
 
 
 def test_rk4_parity_c2():
-    """100 RK4 steps of the vortex (C2) on the GPU against 2 oracle steps compared after 2 GPU steps,
-    then conservation over the full 100 steps."""
+    """100 RK4 steps of the vortex (C2) on the GPU against 100 oracle steps: after 2 steps within
+    1e-12 and after all 100 within 1e-10 of max|U| (rounding differences grow with the number of
+    residual evaluations, 400 here), then discrete conservation over the 100 steps."""
     from oracle import solver
     pr = case("C2")
     ctx = gpu_of(pr)
@@ -120,9 +149,15 @@ def test_rk4_parity_c2():
     for _ in range(2):
         Uo = solver.rk4_step(orc, Uo, pr.dt)
     err = np.abs(U.cpu().numpy() - Uo.numpy()).max()
+    record("C2", "U after 2 RK4 steps", err, 1e-12 * np.abs(Uo.numpy()).max())
     assert err <= 1e-12 * np.abs(Uo.numpy()).max()
     ctx.ldg_rk4(U, pr.dt, 98)
     torch.cuda.synchronize()
+    for _ in range(98):
+        Uo = solver.rk4_step(orc, Uo, pr.dt)
+    err = np.abs(U.cpu().numpy() - Uo.numpy()).max()
+    record("C2", "U after 100 RK4 steps", err, 1e-10 * np.abs(Uo.numpy()).max())
+    assert err <= 1e-10 * np.abs(Uo.numpy()).max()
     geo = orc.geometry(torch.arange(orc.E))
     W = orc.ops.M.sum(1)
     w = torch.as_tensor(np.prod(W[orc.node_coords()], axis=1))

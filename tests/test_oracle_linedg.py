@@ -284,16 +284,8 @@ def test_relabelling_invariance(eq):
 
 # ------------------------------------------------------------------ K21 weights = homogeneous gradient
 def flip_mesh(mesh, seed, frac=0.5):
-    """Reverse two local axes of a random subset of elements (a rotation by 180 degrees
-    in the plane of those axes), so that switch signs S = -1 and reversed face-node maps occur."""
-    rng = np.random.default_rng(seed)
-    E, D = mesh.n_elem, mesh.dim
-    flips = np.zeros((E, D), dtype=bool)
-    for e in np.nonzero(rng.random(E) < frac)[0]:
-        axes = rng.choice(D, size=2, replace=False)
-        flips[e, axes] = True
-    perm = rng.permutation(E)
-    return reorient_elements(mesh, flips, perm)
+    from tests.gpu_cases import flip_mesh as fm
+    return fm(mesh, seed, frac)[0]
 
 
 def apply_k21(d, W, x):

@@ -239,3 +239,42 @@ def test_precond_matrix_is_the_intra_element_restriction(dim):
     for e in sorted({0, int(flipped[0]), d.E - 1}):
         ref = _intra_element_columns(d, K11, K12, gamma, alpha, e) * mask
         assert torch.allclose(At[e], ref, rtol=0, atol=1e-12 * float(ref.abs().max())), e
+
+
+def _heat_problem():
+    """Poisson operator with zero Dirichlet data and no source: dU/dt = R(U) = A U is linear."""
+    mesh = quad_mesh(2, 2, 2, box=((0, 1), (0, 1)), perturb=0.1, seed=3)
+    ph = Physics(EQ_POISSON, 2)
+    d = LineDG(2, 2, mesh.xyz, mesh.face_nbr, mesh.nbr_node, mesh.switch_plus, ph, 0.0, 10.0)
+    U0 = torch.as_tensor(np.sin(3.0 * mesh.xyz[:, 0:1]) * np.cos(2.0 * mesh.xyz[:, 1:2]))
+    K11, K12, K21 = d.jacobian(U0)
+    A = solver.dense_operator(d, K11, K12, K21)
+    return d, U0, A
+
+
+def test_dirk3_is_third_order_against_the_matrix_exponential():
+    """On the linear system dU/dt = A U the DIRK3 step reproduces expm(t A) U0 with error
+    O(dt^3) at fixed t (the tableau's order), so halving dt divides the error by about 8."""
+    import scipy.linalg
+    d, U0, A = _heat_problem()
+    lam = float(np.abs(np.linalg.eigvals(A)).max())
+    T = 4.0 / lam
+    exact = scipy.linalg.expm(T * A) @ U0.reshape(-1).numpy()
+    errs = []
+    for nsteps in (4, 8, 16):
+        U = U0.clone()
+        for _ in range(nsteps):
+            U, st = solver.dirk3_step(d, U, T / nsteps, newton_tol=1e-10)
+        errs.append(float(np.abs(U.reshape(-1).numpy() - exact).max()))
+    r1, r2 = np.log2(errs[0] / errs[1]), np.log2(errs[1] / errs[2])
+    assert r1 > 2.6 and r2 > 2.7, (errs, r1, r2)
+
+
+def test_dirk3_is_l_stable():
+    """A single step with dt far beyond the stiffest mode damps every mode (L-stability:
+    the stability function vanishes at -infinity), where Crank-Nicolson would not."""
+    d, U0, A = _heat_problem()
+    lam = float(np.abs(np.linalg.eigvals(A)).max())
+    lam_min = float(np.abs(np.linalg.eigvals(A)).min())
+    U1, _ = solver.dirk3_step(d, U0, 1e4 / lam_min)
+    assert float(U1.abs().max()) < 1e-3 * float(U0.abs().max())
