@@ -705,6 +705,7 @@ ldg_status ldg_implicit_step(ldg_ctx c, double* U, double* Uprev, double dt, con
   const DevCtx& dc = c->dc;
   const int64_t n = c->ndof;
   auto t_start = std::chrono::steady_clock::now();
+  TRY(ensure_krylov(c, lo->restart));
   TRY(dev_alloc(c, &c->d_st_Un, (size_t)n));
   TRY(dev_alloc(c, &c->d_st_comb, (size_t)n));
   TRY(dev_alloc(c, &c->d_st_K, (size_t)2 * n));

