@@ -127,6 +127,19 @@ ldg_status ldg_jacobian_assemble(ldg_ctx ctx, const double* U_dev, double alpha,
  * Error: LDG_E_NOT_ASSEMBLED. */
 ldg_status ldg_jacvec(ldg_ctx ctx, const double* x_dev, double* y_dev, int32_t exact_fp64);
 
+/* Allocation-free variant of ldg_jacvec, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, result and errors as ldg_jacvec;
+ * the intermediate w = K21 x goes to a static device array of
+ * LDG_NOALLOC_SCRATCH_DOUBLES doubles (64 MiB, held by every GPU the library
+ * runs on until the process ends) instead of context memory, and the call
+ * performs no hipMalloc / hipFree.  It needs E m D Np <= LDG_NOALLOC_SCRATCH_DOUBLES
+ * (e.g. the 16^3 p = 3 Navier-Stokes mesh, 3.9 M) and returns LDG_E_UNSUPPORTED
+ * beyond.  All calls on one GPU share the array: calls that overlap on a GPU
+ * (several streams or threads) race.  The context must have been assembled. */
+#define LDG_NOALLOC_SCRATCH_DOUBLES (8 * 1024 * 1024)
+ldg_status ldg_jacvec_noalloc(ldg_ctx ctx, const double* x_dev, double* y_dev, int32_t exact_fp64);
+
 /* Preconditioner of Section 4.2: the block-Jacobi matrix A~ that keeps A only
  * on each element's line pattern (no K12 K21 fill, no inter-element
  * coupling), applied as z = P^{-1} r with its block ILU(0) factors (per

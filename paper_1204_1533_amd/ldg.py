@@ -95,6 +95,7 @@ _SIGS = {
     "ldg_residual": (ctypes.c_int, [_P, _P, _P, _P]),
     "ldg_jacobian_assemble": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_int32]),
     "ldg_jacvec": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32]),
+    "ldg_jacvec_noalloc": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32]),
     "ldg_precond_apply": (ctypes.c_int, [_P, _P, _P]),
     "ldg_export_operators": (ctypes.c_int, [_P, _P, _P, _P]),
     "ldg_newton_step": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.c_double,
@@ -227,6 +228,9 @@ class Context:
 
     def ldg_jacvec(self, x, y, exact_fp64=False):
         self._check(self.lib.ldg_jacvec(self.h, _ptr(x), _ptr(y), int(exact_fp64)))
+
+    def ldg_jacvec_noalloc(self, x, y, exact_fp64=False):
+        self._check(self.lib.ldg_jacvec_noalloc(self.h, _ptr(x), _ptr(y), int(exact_fp64)))
 
     def ldg_precond_apply(self, r, z):
         self._check(self.lib.ldg_precond_apply(self.h, _ptr(r), _ptr(z)))
