@@ -502,90 +502,240 @@ __global__ void __launch_bounds__(64) factor_kernel(int64_t E, void* __restrict_
   }
 }
 
+// Registers of one factor row: NJP entries of precision FP, loaded 4 at a time
+// (8 bytes for BF16, 16 for FP32, 32 for FP64) from the apply layout.
+template <int FP, int NJP> struct RowRegs;
+template <int NJP> struct RowRegs<PREC_BF16, NJP> {
+  uint2 v[NJP / 4];
+  __device__ __forceinline__ void load(const void* F, int64_t base, int NR) {
+    const uint2* p = reinterpret_cast<const uint2*>(F);
+#pragma unroll
+    for (int ch = 0; ch < NJP / 4; ++ch) v[ch] = p[(base + (int64_t)ch * NR * 4) / 4];
+  }
+  // hides the values from the compiler so that their conversion is not hoisted out of the level loops
+  __device__ __forceinline__ void opaque() {
+#pragma unroll
+    for (int ch = 0; ch < NJP / 4; ++ch) asm volatile("" : "+v"(v[ch].x), "+v"(v[ch].y));
+  }
+  __device__ __forceinline__ double get(int j) const {
+    const uint32_t w = (j & 2) ? v[j >> 2].y : v[j >> 2].x;
+    return bf16_to_f32((uint16_t)((j & 1) ? (w >> 16) : (w & 0xFFFFu)));
+  }
+};
+template <int NJP> struct RowRegs<PREC_F32, NJP> {
+  float4 v[NJP / 4];
+  __device__ __forceinline__ void load(const void* F, int64_t base, int NR) {
+    const float4* p = reinterpret_cast<const float4*>(F);
+#pragma unroll
+    for (int ch = 0; ch < NJP / 4; ++ch) v[ch] = p[(base + (int64_t)ch * NR * 4) / 4];
+  }
+  __device__ __forceinline__ void opaque() {
+#pragma unroll
+    for (int ch = 0; ch < NJP / 4; ++ch) asm volatile("" : "+v"(v[ch].x), "+v"(v[ch].y), "+v"(v[ch].z), "+v"(v[ch].w));
+  }
+  __device__ __forceinline__ double get(int j) const {
+    const float4& q = v[j >> 2];
+    const int k = j & 3;
+    return k == 0 ? q.x : (k == 1 ? q.y : (k == 2 ? q.z : q.w));
+  }
+};
+template <int NJP> struct RowRegs<PREC_F64, NJP> {
+  double2 v[NJP / 2];
+  __device__ __forceinline__ void load(const void* F, int64_t base, int NR) {
+    const double2* p = reinterpret_cast<const double2*>(F);
+#pragma unroll
+    for (int ch = 0; ch < NJP / 4; ++ch) {
+      v[2 * ch] = p[(base + (int64_t)ch * NR * 4) / 2];
+      v[2 * ch + 1] = p[(base + (int64_t)ch * NR * 4) / 2 + 1];
+    }
+  }
+  __device__ __forceinline__ void opaque() {}
+  __device__ __forceinline__ double get(int j) const { return (j & 1) ? v[j >> 1].y : v[j >> 1].x; }
+};
+
+template <int D, int P>
+__device__ __forceinline__ int node_level(int a) {
+  constexpr int N1 = P + 1;
+  int s = 0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    s += a % N1;
+    a /= N1;
+  }
+  return s;
+}
+
+// Rows of the largest level of a (p+1)^D node grid: nodes with coordinate sum
+// floor(D p / 2), times the m components.
+template <int D, int P, int EQ>
+__host__ __device__ constexpr int max_level_rows() {
+  int best = 0;
+  for (int L = 0; L <= D * P; ++L) {
+    int cnt = 0;
+    for (int a = 0; a < ipow(P + 1, D); ++a) {
+      int s = 0, r = a;
+      for (int d = 0; d < D; ++d) {
+        s += r % (P + 1);
+        r /= (P + 1);
+      }
+      cnt += s == L;
+    }
+    best = cnt > best ? cnt : best;
+  }
+  return best * Eq<D, EQ>::M;
+}
+template <int D, int P, int EQ>
+struct ApplyShape {
+  static constexpr int TPE = max_level_rows<D, P, EQ>();  // work items per element: one level's rows
+  static constexpr int EPB = TPE >= 128 ? 1 : 128 / TPE;  // elements per workgroup
+  static constexpr int NT = (EPB * TPE + 63) / 64 * 64;
+};
+
+// z = (L U)^{-1} r element by element, by level: rows with equal a_0 + .. +
+// a_{D-1} are independent.  The work items of an element take the rows of one
+// level at a time (one row each: node a, component c); the factor rows are
+// stored in level order, so a level's rows are one contiguous run read with
+// 8- to 32-byte loads, and the next level's rows are fetched while the current
+// one is computed.  y_a = r_a - sum_{k < a} L_ak y_k, then
+// z_a = U_aa^{-1} (y_a - sum_{j > a} U_aj z_j) with the inverse diagonal block
+// stored in the diagonal slot; y and z live in LDS in natural order.
 template <int D, int P, int EQ, int FP>
-__global__ void __launch_bounds__(64) apply_kernel(int64_t E, const void* __restrict__ F, const double* __restrict__ r,
-                                                   double* __restrict__ z) {
-  constexpr int N1 = P + 1, NP = ipow(N1, D), M = Eq<D, EQ>::M;
-  constexpr int NSL = D * P + 1, RPP = 64 / M, NSLMM = NSL * M * M;
-  // F: element-major copy of the factors, [E Np][slot][c][c'] (one element's
-  // factors are contiguous, so a workgroup reads whole cache lines)
-  __shared__ int rows[NP];
-  __shared__ int off[D * P + 2];
-  __shared__ double sy[NP * M];
-  __shared__ double st[NP * M];
-  const int64_t e = blockIdx.x;
-  const int lane = threadIdx.x;
-  if (lane == 0) level_table<D, P>(rows, off);
-  for (int i = lane; i < NP * M; i += 64) sy[i] = r[e * M * NP + (i % M) * NP + i / M];
+__global__ void __launch_bounds__((ApplyShape<D, P, EQ>::NT)) apply_kernel(LevelOrder ord, int64_t E,
+                                                                          const void* __restrict__ F,
+                                                                          const double* __restrict__ r,
+                                                                          double* __restrict__ z) {
+  using S = FacShape<D, P, EQ>;
+  using A = ApplyShape<D, P, EQ>;
+  constexpr int N1 = P + 1, NP = S::NP, M = S::M, NSL = S::NSL, NR = S::NR, NJP = S::NJP;
+  constexpr int TPE = A::TPE, EPB = A::EPB, NL = D * P;
+  __shared__ double sy[EPB * NR];
+  __shared__ double st[EPB * NR];
+  const int tid = threadIdx.x;
+  const int le = tid / TPE, lane = tid % TPE;
+  const int64_t e = (int64_t)blockIdx.x * EPB + le;
+  const bool live = le < EPB && e < E;
+  double* y = sy + (le < EPB ? le : 0) * NR;
+  double* t = st + (le < EPB ? le : 0) * NR;
+  if (live)
+    for (int i = lane; i < NR; i += TPE) y[i] = r[e * NR + i];
   __syncthreads();
-  // forward: y_i = r_i - sum_{k < i on i's lines} L_ik y_k
-  for (int L = 1; L <= D * P; ++L) {
-    const int nrow = off[L + 1] - off[L];
-    for (int r0 = 0; r0 < nrow; r0 += RPP) {
-      const int ri = r0 + lane / M, c = lane % M;
-      double acc = 0.0;
-      int i = 0;
-      const bool active = (lane < RPP * M) && ri < nrow;
-      if (active) {
-        i = rows[off[L] + ri];
-        const int64_t gi = e * NP + i;
-        const int self_i = i % N1;
-        acc = sy[i * M + c];
-        // all line slots with compile-time bounds; the strictly lower ones
-        // (column before i in natural order) count, so every load of the row
-        // can be in flight at once.  Slot order = direction-major, position-
-        // ascending, the order of the elimination.
+  // forward sweep over levels 1..NL (level 0 has no lower entries)
+  RowRegs<FP, NJP> f, fn;
+  {
+    const int row = ord.off[1] * M + lane;
+    if (live && row < ord.off[2] * M) f.load(F, fac_index(e, row, 0, NR, NJP), NR);
+  }
+  for (int L = 1; L <= NL; ++L) {
+    const int row = ord.off[L] * M + lane;
+    const bool act = live && row < ord.off[L + 1] * M;
+    if (L < NL) {
+      const int rn = ord.off[L + 1] * M + lane;
+      if (live && rn < ord.off[L + 2] * M) fn.load(F, fac_index(e, rn, 0, NR, NJP), NR);
+    }
+    if (act) {
+      const int a = ord.node[row / M], c = row % M;
+      double acc = y[c * NP + a];
 #pragma unroll
-        for (int s = 0; s < NSL; ++s) {
-          const int k = slot_col<D, P>(i, s);
-          const double msk = k < i ? 1.0 : 0.0;
-          double t = 0.0;
+      for (int s = 0; s < NSL; ++s) {
+        const int k = slot_col<D, P>(a, s);
+        if (k < a) {
+          double tt = 0.0;  // one block row at a time: short dependency chains
 #pragma unroll
-          for (int q = 0; q < M; ++q) t += Store<FP>::get(F, gi * NSLMM + (s * M + c) * M + q) * sy[k * M + q];
-          acc -= msk * t;
+          for (int q = 0; q < M; ++q) tt += f.get(s * M + q) * y[q * NP + k];
+          acc -= tt;
         }
       }
-      __syncthreads();
-      if (active) sy[i * M + c] = acc;
-      __syncthreads();
+      y[c * NP + a] = acc;
     }
+    __syncthreads();
+    f = fn;
   }
-  // backward: z_i = Uinv_ii (y_i - sum_{j > i on i's lines} U_ij z_j); z overwrites y
-  for (int L = D * P; L >= 0; --L) {
-    const int nrow = off[L + 1] - off[L];
-    for (int r0 = 0; r0 < nrow; r0 += RPP) {
-      const int ri = r0 + lane / M, c = lane % M;
-      const bool active = (lane < RPP * M) && ri < nrow;
-      int i = 0;
-      if (active) {
-        i = rows[off[L] + ri];
-        const int64_t gi = e * NP + i;
-        const int self_i = i % N1;
-        double acc = sy[i * M + c];
+  // backward sweep over levels NL..0
+  {
+    const int row = ord.off[NL] * M + lane;
+    if (live && row < ord.off[NL + 1] * M) f.load(F, fac_index(e, row, 0, NR, NJP), NR);
+  }
+  for (int L = NL; L >= 0; --L) {
+    const int row = ord.off[L] * M + lane;
+    const bool act = live && row < ord.off[L + 1] * M;
+    if (L > 0) {
+      const int rn = ord.off[L - 1] * M + lane;
+      if (live && rn < ord.off[L] * M) fn.load(F, fac_index(e, rn, 0, NR, NJP), NR);
+    }
+    int a = 0, c = 0;
+    if (act) {
+      a = ord.node[row / M];
+      c = row % M;
+      double acc = y[c * NP + a];
 #pragma unroll
-        for (int s = 0; s < NSL; ++s) {
-          const int j = slot_col<D, P>(i, s);
-          const double msk = j > i ? 1.0 : 0.0;
-          double t = 0.0;
+      for (int s = 0; s < NSL; ++s) {
+        const int j = slot_col<D, P>(a, s);
+        if (j > a) {
+          double tt = 0.0;
 #pragma unroll
-          for (int q = 0; q < M; ++q) t += Store<FP>::get(F, gi * NSLMM + (s * M + c) * M + q) * sy[j * M + q];
-          acc -= msk * t;
+          for (int q = 0; q < M; ++q) tt += f.get(s * M + q) * y[q * NP + j];
+          acc -= tt;
         }
-        st[i * M + c] = acc;
       }
-      __syncthreads();
-      if (active) {
-        const int64_t gi = e * NP + i;
-        const int self_i = i % N1;
-        double v = 0.0;
-#pragma unroll
-        for (int q = 0; q < M; ++q) v += Store<FP>::get(F, gi * NSLMM + (self_i * M + c) * M + q) * st[i * M + q];
-        sy[i * M + c] = v;
-      }
-      __syncthreads();
+      t[c * NP + a] = acc;
     }
+    __syncthreads();
+    if (act) {
+      const int self = a % N1;
+      double v = 0.0;
+#pragma unroll
+      for (int s = 0; s < N1; ++s)
+        if (s == self) {
+#pragma unroll
+          for (int q = 0; q < M; ++q) v += f.get(s * M + q) * t[q * NP + a];
+        }
+      y[c * NP + a] = v;
+    }
+    __syncthreads();
+    f = fn;
   }
-  for (int i = lane; i < NP * M; i += 64) z[e * M * NP + (i % M) * NP + i / M] = sy[i];
+  if (live)
+    for (int i = lane; i < NR; i += TPE) z[e * NR + i] = y[i];
+}
+
+// element-major factors [E Np][slot][c][c'] -> apply layout (zero padding)
+template <int PIN, int POUT>
+__global__ void em_to_fac_kernel(LevelOrder ord, const void* __restrict__ in, void* __restrict__ out, int64_t E,
+                                 int NP, int M, int NSL) {
+  const int NR = NP * M, NJ = NSL * M, NJP = (NJ + 3) / 4 * 4;
+  const int64_t total = E * (int64_t)NJP * NR;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int jj = (int)(i & 3);
+    const int64_t q = i >> 2;
+    const int rr = (int)(q % NR);
+    const int64_t q2 = q / NR;
+    const int ch = (int)(q2 % (NJP / 4));
+    const int64_t e = q2 / (NJP / 4);
+    const int j = ch * 4 + jj;
+    double v = 0.0;
+    if (j < NJ) {
+      const int a = ord.node[rr / M], c = rr % M, slot = j / M, cp = j % M;
+      v = Store<PIN>::get(in, ((e * NP + a) * NSL + slot) * (int64_t)(M * M) + c * M + cp);
+    }
+    Store<POUT>::put(out, i, v);
+  }
+}
+
+// apply layout -> FP64 [E][Np][slot][c][c'] (the exchange layout of ldg_export_operators)
+template <int PIN>
+__global__ void fac_to_em64_kernel(LevelOrder ord, const void* __restrict__ in, double* __restrict__ out, int64_t E,
+                                   int NP, int M, int NSL) {
+  const int NR = NP * M, NJP = (NSL * M + 3) / 4 * 4;
+  const int64_t total = E * NP * (int64_t)NSL * M * M;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int cp = (int)(i % M);
+    const int c = (int)((i / M) % M);
+    const int slot = (int)((i / (M * M)) % NSL);
+    const int64_t gn = i / ((int64_t)M * M * NSL);
+    const int64_t e = gn / NP;
+    const int a = (int)(gn % NP);
+    out[i] = Store<PIN>::get(in, fac_index(e, ord.rank[a] * M + c, slot * M + cp, NR, NJP));
+  }
 }
 
 template <int PIN, int POUT>
@@ -623,21 +773,25 @@ static unsigned copy_grid(int64_t n) {
 }
 
 // A~ is formed node-fastest in Fwork, copied (At_copy, optional) in FP32,
-// transposed to the element-major layout and factorised there in place; the
-// factors end in Fem in storage precision fprec.  Fwork holds nF entries of
-// the factorisation precision (FP64 for fprec = F64, FP32 otherwise) and, for
-// BF16, a second FP32 array of nF after them (the element-major work copy).
+// transposed to the element-major layout in the second half of Fwork and
+// factorised there in place, then rearranged into the apply layout in Fem, in
+// storage precision fprec.  Fwork holds 2 nF entries of the factorisation
+// precision (FP64 for fprec = F64, FP32 otherwise).
 hipError_t launch_precond_factor(const DevCtx& dc, const void* K11, const void* K12, int prec, double alpha,
                                  double gamma, void* Fwork, int fprec, void* Fem, float* At_copy) {
   const int64_t NN = dc.E * dc.NP;
-  const int nq = (dc.D * dc.P + 1) * dc.M * dc.M;
+  const int nsl = dc.D * dc.P + 1;
+  const int nq = nsl * dc.M * dc.M;
   const int64_t nF = NN * (int64_t)nq;
+  const int NR = dc.NP * dc.M, NJP = (nsl * dc.M + 3) / 4 * 4;
+  const int64_t nFac = dc.E * (int64_t)NR * NJP;
   const dim3 tgrid((unsigned)((NN + 63) / 64), (unsigned)((nq + 31) / 32));
   LDG_DISPATCH(dc, {
     using L = FormLayout<D, P, EQ>;
     const size_t bytes = Eq<D, EQ>::VIS ? L::bytes : 0;
     LDG_PREC_DISPATCH(prec, {
       if (fprec == PREC_F64) {
+        double* em = (double*)Fwork + nF;
         auto k = form_kernel<D, P, EQ, PR, PREC_F64>;
         if (bytes > 65536) hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         hipLaunchKernelGGL(k, dim3((unsigned)dc.E), dim3(NT_ELEM), bytes, dc.stream, dc.ops, dc.mp, K11, K12, alpha,
@@ -645,11 +799,13 @@ hipError_t launch_precond_factor(const DevCtx& dc, const void* K11, const void* 
         if (At_copy)
           hipLaunchKernelGGL((convert_kernel<PREC_F64, PREC_F32>), dim3(copy_grid(nF)), dim3(256), 0, dc.stream, Fwork,
                              At_copy, nF);
-        hipLaunchKernelGGL((relayout_kernel<PREC_F64>), tgrid, dim3(256), 0, dc.stream, Fwork, Fem, NN, nq);
+        hipLaunchKernelGGL((relayout_kernel<PREC_F64>), tgrid, dim3(256), 0, dc.stream, Fwork, em, NN, nq);
         hipLaunchKernelGGL((factor_kernel<D, P, EQ, PREC_F64>), dim3((unsigned)dc.E), dim3(64), 0, dc.stream, dc.E,
-                           Fem);
+                           em);
+        hipLaunchKernelGGL((em_to_fac_kernel<PREC_F64, PREC_F64>), dim3(copy_grid(nFac)), dim3(256), 0, dc.stream, dc.lev,
+                           em, Fem, dc.E, dc.NP, dc.M, nsl);
       } else {
-        void* em = fprec == PREC_F32 ? Fem : (void*)((float*)Fwork + nF);
+        float* em = (float*)Fwork + nF;
         auto k = form_kernel<D, P, EQ, PR, PREC_F32>;
         if (bytes > 65536) hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         hipLaunchKernelGGL(k, dim3((unsigned)dc.E), dim3(NT_ELEM), bytes, dc.stream, dc.ops, dc.mp, K11, K12, alpha,
@@ -660,28 +816,35 @@ hipError_t launch_precond_factor(const DevCtx& dc, const void* K11, const void* 
         hipLaunchKernelGGL((relayout_kernel<PREC_F32>), tgrid, dim3(256), 0, dc.stream, Fwork, em, NN, nq);
         hipLaunchKernelGGL((factor_kernel<D, P, EQ, PREC_F32>), dim3((unsigned)dc.E), dim3(64), 0, dc.stream, dc.E, em);
         if (fprec == PREC_BF16)
-          hipLaunchKernelGGL((convert_kernel<PREC_F32, PREC_BF16>), dim3(copy_grid(nF)), dim3(256), 0, dc.stream, em,
-                             Fem, nF);
+          hipLaunchKernelGGL((em_to_fac_kernel<PREC_F32, PREC_BF16>), dim3(copy_grid(nFac)), dim3(256), 0, dc.stream,
+                             dc.lev, em, Fem, dc.E, dc.NP, dc.M, nsl);
+        else
+          hipLaunchKernelGGL((em_to_fac_kernel<PREC_F32, PREC_F32>), dim3(copy_grid(nFac)), dim3(256), 0, dc.stream,
+                             dc.lev, em, Fem, dc.E, dc.NP, dc.M, nsl);
       }
       return hipGetLastError();
     })
   })
 }
 
-// element-major factors -> FP64 [E][Np][slot][c][c'] (the same order)
+// apply-layout factors -> FP64 [E][Np][slot][c][c']
 hipError_t launch_factors_to_f64(const DevCtx& dc, const void* Fem, int fprec, double* out) {
-  const int64_t n = dc.E * dc.NP * (int64_t)((dc.D * dc.P + 1) * dc.M * dc.M);
+  const int nsl = dc.D * dc.P + 1;
+  const int64_t n = dc.E * dc.NP * (int64_t)(nsl * dc.M * dc.M);
   LDG_PREC_DISPATCH(fprec, {
-    hipLaunchKernelGGL((convert_kernel<PR, PREC_F64>), dim3(copy_grid(n)), dim3(256), 0, dc.stream, Fem, out, n);
+    hipLaunchKernelGGL((fac_to_em64_kernel<PR>), dim3(copy_grid(n)), dim3(256), 0, dc.stream, dc.lev, Fem, out, dc.E,
+                       dc.NP, dc.M, nsl);
     return hipGetLastError();
   })
 }
 
-// Fem: the element-major factors written by launch_precond_factor.
+// Fem: the factors in the apply layout written by launch_precond_factor.
 hipError_t launch_precond_apply(const DevCtx& dc, const void* F, int fprec, const double* r, double* z) {
   LDG_DISPATCH(dc, {
+    using A = ApplyShape<D, P, EQ>;
+    const unsigned grid = (unsigned)((dc.E + A::EPB - 1) / A::EPB);
     LDG_PREC_DISPATCH(fprec, {
-      hipLaunchKernelGGL((apply_kernel<D, P, EQ, PR>), dim3((unsigned)dc.E), dim3(64), 0, dc.stream, dc.E, F, r, z);
+      hipLaunchKernelGGL((apply_kernel<D, P, EQ, PR>), dim3(grid), dim3(A::NT), 0, dc.stream, dc.lev, dc.E, F, r, z);
       return hipGetLastError();
     })
   })

@@ -33,6 +33,16 @@ struct LineOps {
   double Dn[N1MAX][N1MAX];  // phi_j'(s_i): nodal derivative (mapping gradient)
 };
 
+// Nodes of an element sorted by level a_0 + .. + a_{D-1} (the independent
+// sets of the block ILU(0) sweeps), ascending node index within a level:
+// node[off[L] .. off[L+1]) is level L, rank[a] the position of node a.
+constexpr int NPMAX = 125;  // (p+1)^D for p <= 4
+struct LevelOrder {
+  int16_t node[NPMAX];
+  int16_t rank[NPMAX];
+  int16_t off[3 * 4 + 2];
+};
+
 struct MeshParams {
   int64_t E;
   double gamma, mu, prandtl, c11i, c11d;

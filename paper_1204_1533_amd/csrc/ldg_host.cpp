@@ -171,6 +171,25 @@ ldg_status ldg_create(const ldg_problem_desc* d, void* stream, ldg_ctx* out) {
   dc.E = E;
   dc.stream = (hipStream_t)stream;
   if (!build_line_ops(P, d->node_family, dc.ops, nullptr)) return bad(LDG_E_UNSUPPORTED, "1-D operators for this p");
+  {
+    // nodes by level i + j (+ k), ascending within a level
+    int pos = 0;
+    for (int L = 0; L <= D * P; ++L) {
+      dc.lev.off[L] = (int16_t)pos;
+      for (int a = 0; a < NP; ++a) {
+        int sum = 0, r = a;
+        for (int k = 0; k < D; ++k) {
+          sum += r % N1;
+          r /= N1;
+        }
+        if (sum == L) {
+          dc.lev.rank[a] = (int16_t)pos;
+          dc.lev.node[pos++] = (int16_t)a;
+        }
+      }
+    }
+    dc.lev.off[D * P + 1] = (int16_t)pos;
+  }
   c->ndof = E * M * NP;
   c->nq = c->ndof * D;
   c->nnode = E * NP;
@@ -261,11 +280,13 @@ static ldg_status assemble(ldg_ctx c, const double* U, double alpha, double gamm
   TRY(grow(c, &c->d_K12, &c->capK12, es * (size_t)ns12 * dc.M * dc.M * dc.D * c->nnode));
   const int fprec = prec;
   const size_t nF = (size_t)nsF * dc.M * dc.M * c->nnode;
-  // A~ is formed node-fastest in d_F (FP64 for FP64 storage, FP32 otherwise;
-  // for BF16 an element-major FP32 copy follows it) and factorised into d_Fem
-  const size_t fbytes = fprec == LDG_F64 ? 8 * nF : (fprec == LDG_F32 ? 4 * nF : 8 * nF);
+  // A~ is formed node-fastest in d_F (FP64 for FP64 storage, FP32 otherwise),
+  // factorised in an element-major copy after it, and the factors are stored
+  // in d_Fem in the apply layout (rows padded to a multiple of 4 entries)
+  const size_t fbytes = (fprec == LDG_F64 ? 8 : 4) * 2 * nF;
+  const size_t nFac = (size_t)dc.E * dc.NP * dc.M * ((nsF * dc.M + 3) / 4 * 4);
   TRY(grow(c, &c->d_F, &c->capF, fbytes));
-  TRY(grow(c, &c->d_Fem, &c->capFem, elem_size(fprec) * nF));
+  TRY(grow(c, &c->d_Fem, &c->capFem, elem_size(fprec) * nFac));
   TRY(dev_alloc(c, &c->d_Ua, (size_t)c->ndof));
   TRY(dev_alloc(c, &c->d_Qa, (size_t)c->nq));
   HIPCK(c, hipMemcpyAsync(c->d_Ua, U, sizeof(double) * c->ndof, hipMemcpyDeviceToDevice, dc.stream));

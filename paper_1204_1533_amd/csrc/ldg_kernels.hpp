@@ -12,6 +12,7 @@ struct DevCtx {
   int D, P, EQ, M, N1, NP, NL, NG;
   int64_t E;
   LineOps ops;
+  LevelOrder lev;
   MeshParams mp;
   hipStream_t stream;
 };
@@ -25,6 +26,26 @@ __host__ __device__ constexpr int elems_per_block(int NP, int M) {
   int e = 512 / (NP * M);
   return e < 1 ? 1 : (e > 16 ? 16 : e);
 }
+
+// Layout of the BILU(0) factors read by the preconditioner apply.  Per
+// element the NR = M Np factor rows r = M rank[a] + c (component c of node a,
+// nodes in level order, LevelOrder) hold
+// the NJ = (D p + 1) M entries j = slot M + c' of their line-slot blocks
+// (slot order of the line pattern, the diagonal slot holding the inverse of
+// the U diagonal block), padded with zeros to NJP = 4 ceil(NJ / 4).  Stored
+// as [E][NJP / 4][NR][4]: a row's entries come in chunks of 4, and the same
+// chunk of consecutive rows is contiguous, so that one load per chunk by
+// consecutive rows reads one contiguous run.
+__host__ __device__ constexpr int64_t fac_index(int64_t e, int r, int j, int NR, int NJP) {
+  return ((e * (NJP / 4) + (j >> 2)) * NR + r) * 4 + (j & 3);
+}
+template <int D, int P, int EQ>
+struct FacShape {
+  static constexpr int NP = ipow(P + 1, D), M = Eq<D, EQ>::M, NSL = D * P + 1;
+  static constexpr int NR = NP * M, NJ = NSL * M, NJP = (NJ + 3) / 4 * 4;
+  static constexpr int EPB = NR >= 512 ? 1 : 512 / NR;  // elements per workgroup of the apply
+  static constexpr int NT = (EPB * NR + 63) / 64 * 64;
+};
 
 hipError_t launch_gradient(const DevCtx& c, const double* U, double* Q, bool homogeneous);
 hipError_t launch_residual(const DevCtx& c, const double* U, const double* Q, double* R);
@@ -40,8 +61,8 @@ hipError_t launch_jacvec(const DevCtx& c, const void* K11, const void* K12, int 
                          const double* x, const double* w, double* y);
 
 // Preconditioner A~ (line pattern) formed from the stored K11/K12 and the
-// K21 weights (node-fastest in Fwork), then factorised by block ILU(0) in the
-// element-major layout [E Np][slot][c][c']: factors in Fem (precision fprec).
+// K21 weights (node-fastest in Fwork), then factorised by block ILU(0): the
+// factors end in Fem in the apply layout above (precision fprec).
 hipError_t launch_precond_factor(const DevCtx& c, const void* K11, const void* K12, int prec, double alpha,
                                  double gamma, void* Fwork, int fprec, void* Fem, float* At_copy);
 hipError_t launch_factors_to_f64(const DevCtx& c, const void* Fem, int fprec, double* out);
