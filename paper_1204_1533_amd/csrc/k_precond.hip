@@ -774,9 +774,9 @@ static unsigned copy_grid(int64_t n) {
 
 // A~ is formed node-fastest in Fwork, copied (At_copy, optional) in FP32,
 // transposed to the element-major layout in the second half of Fwork and
-// factorised there in place, then rearranged into the apply layout in Fem, in
-// storage precision fprec.  Fwork holds 2 nF entries of the factorisation
-// precision (FP64 for fprec = F64, FP32 otherwise).
+// factorised there in place (FP64 arithmetic for FP64 factors, FP32
+// otherwise), then rearranged into the apply layout in Fem in storage
+// precision fprec.
 hipError_t launch_precond_factor(const DevCtx& dc, const void* K11, const void* K12, int prec, double alpha,
                                  double gamma, void* Fwork, int fprec, void* Fem, float* At_copy) {
   const int64_t NN = dc.E * dc.NP;

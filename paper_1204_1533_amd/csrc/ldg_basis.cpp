@@ -167,4 +167,30 @@ bool build_line_ops(int p, int node_family, LineOps& ops, std::vector<double>* n
   return true;
 }
 
+// Nodes of a (p+1)^D element grouped by level i + j (+ k), ascending within a
+// level (the order of the factor rows read by the preconditioner apply).
+void build_level_order(int D, int P, LevelOrder& lv) {
+  const int N1 = P + 1;
+  int NP = 1;
+  for (int k = 0; k < D; ++k) NP *= N1;
+  auto level = [&](int a) {
+    int s = 0;
+    for (int k = 0; k < D; ++k) {
+      s += a % N1;
+      a /= N1;
+    }
+    return s;
+  };
+  int pos = 0;
+  for (int L = 0; L <= D * P; ++L) {
+    lv.off[L] = (int16_t)pos;
+    for (int a = 0; a < NP; ++a)
+      if (level(a) == L) {
+        lv.rank[a] = (int16_t)pos;
+        lv.node[pos++] = (int16_t)a;
+      }
+  }
+  lv.off[D * P + 1] = (int16_t)pos;
+}
+
 }  // namespace ldg

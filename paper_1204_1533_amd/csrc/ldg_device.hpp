@@ -19,8 +19,8 @@ namespace ldg {
 constexpr int N1MAX = 5;  // p <= 4
 constexpr int NGMAX = 7;  // ceil((3*4+1)/2)
 
-constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
-constexpr int n_gauss(int p) { return (3 * p + 2) / 2; }
+__host__ __device__ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+__host__ __device__ constexpr int n_gauss(int p) { return (3 * p + 2) / 2; }
 
 // ---------------------------------------------------------------- 1-D operators
 // Passed by value to every kernel (kernel-argument segment).
@@ -57,13 +57,13 @@ struct MeshParams {
 // ---------------------------------------------------------------- node indexing
 // node(n, l, t): position t on line l of direction n.
 template <int D, int N1>
-__device__ __forceinline__ int line_node(int n, int l, int t) {
+__host__ __device__ inline int line_node(int n, int l, int t) {
   int s = 1;
   for (int k = 0; k < n; ++k) s *= N1;
   return (l % s) + t * s + (l / s) * s * N1;
 }
 template <int N1>
-__device__ __forceinline__ void node_line(int node, int n, int& l, int& t) {
+__host__ __device__ inline void node_line(int node, int n, int& l, int& t) {
   int s = 1;
   for (int k = 0; k < n; ++k) s *= N1;
   t = (node / s) % N1;
@@ -87,7 +87,7 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t G) {
 // for each further direction n, p slots for the other nodes of its direction-n line.
 // column node of line slot `slot` for row node a (within the element)
 template <int D, int P>
-__device__ __forceinline__ int slot_col(int a, int slot) {
+__host__ __device__ inline int slot_col(int a, int slot) {
   constexpr int N1 = P + 1;
   if (slot < N1) return line_node<D, N1>(0, a / N1, slot);
   const int n = 1 + (slot - N1) / P, r = (slot - N1) % P;
@@ -96,7 +96,7 @@ __device__ __forceinline__ int slot_col(int a, int slot) {
   return line_node<D, N1>(n, l, r < t ? r : r + 1);
 }
 template <int N1>
-__device__ __forceinline__ int slot_of(int n, int t, int tp, int self) {
+__host__ __device__ inline int slot_of(int n, int t, int tp, int self) {
   // slot of column position tp on the row's direction-n line; the row sits at t
   if (tp == t) return self;
   return n == 0 ? tp : N1 + (n - 1) * (N1 - 1) + (tp < t ? tp : tp - 1);
@@ -377,7 +377,7 @@ __device__ __forceinline__ void roe_flux(const T* uR, const T* uL, const double*
 // ---------------------------------------------------------------- metric
 // Row n of the cofactor matrix of G (G[a][b] = dx_a/dX_b): a_n = J G^{-T} N_n.
 template <int D>
-__device__ __forceinline__ void cofactor_row(const double G[D][D], int n, double* a) {
+__host__ __device__ inline void cofactor_row(const double G[D][D], int n, double* a) {
   if constexpr (D == 2) {
     // adj(G) = [[G11, -G01], [-G10, G00]]; row n of J G^{-1}
     if (n == 0) { a[0] = G[1][1]; a[1] = -G[0][1]; }
@@ -391,7 +391,7 @@ __device__ __forceinline__ void cofactor_row(const double G[D][D], int n, double
   }
 }
 template <int D>
-__device__ __forceinline__ double det(const double G[D][D]) {
+__host__ __device__ inline double det(const double G[D][D]) {
   if constexpr (D == 2) return G[0][0] * G[1][1] - G[0][1] * G[1][0];
   else
     return G[0][0] * (G[1][1] * G[2][2] - G[1][2] * G[2][1]) - G[0][1] * (G[1][0] * G[2][2] - G[1][2] * G[2][0]) +

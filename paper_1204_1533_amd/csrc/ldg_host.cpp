@@ -15,6 +15,7 @@
 
 namespace ldg {
 bool build_line_ops(int p, int node_family, LineOps& ops, std::vector<double>* nodes_out);
+void build_level_order(int D, int P, LevelOrder& lv);
 }
 
 using namespace ldg;
@@ -171,25 +172,7 @@ ldg_status ldg_create(const ldg_problem_desc* d, void* stream, ldg_ctx* out) {
   dc.E = E;
   dc.stream = (hipStream_t)stream;
   if (!build_line_ops(P, d->node_family, dc.ops, nullptr)) return bad(LDG_E_UNSUPPORTED, "1-D operators for this p");
-  {
-    // nodes by level i + j (+ k), ascending within a level
-    int pos = 0;
-    for (int L = 0; L <= D * P; ++L) {
-      dc.lev.off[L] = (int16_t)pos;
-      for (int a = 0; a < NP; ++a) {
-        int sum = 0, r = a;
-        for (int k = 0; k < D; ++k) {
-          sum += r % N1;
-          r /= N1;
-        }
-        if (sum == L) {
-          dc.lev.rank[a] = (int16_t)pos;
-          dc.lev.node[pos++] = (int16_t)a;
-        }
-      }
-    }
-    dc.lev.off[D * P + 1] = (int16_t)pos;
-  }
+  build_level_order(D, P, dc.lev);
   c->ndof = E * M * NP;
   c->nq = c->ndof * D;
   c->nnode = E * NP;

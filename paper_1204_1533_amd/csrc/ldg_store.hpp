@@ -28,20 +28,20 @@ __host__ __device__ inline float bf16_to_f32(uint16_t h) {
 template <int PREC> struct Store;
 template <> struct Store<PREC_F64> {
   typedef double type;
-  static __device__ __forceinline__ void put(void* p, int64_t i, double v) { ((double*)p)[i] = v; }
-  static __device__ __forceinline__ double get(const void* p, int64_t i) { return ((const double*)p)[i]; }
+  static __host__ __device__ inline void put(void* p, int64_t i, double v) { ((double*)p)[i] = v; }
+  static __host__ __device__ inline double get(const void* p, int64_t i) { return ((const double*)p)[i]; }
 };
 template <> struct Store<PREC_F32> {
   typedef float type;
-  static __device__ __forceinline__ void put(void* p, int64_t i, double v) { ((float*)p)[i] = (float)v; }
-  static __device__ __forceinline__ double get(const void* p, int64_t i) { return ((const float*)p)[i]; }
+  static __host__ __device__ inline void put(void* p, int64_t i, double v) { ((float*)p)[i] = (float)v; }
+  static __host__ __device__ inline double get(const void* p, int64_t i) { return ((const float*)p)[i]; }
 };
 template <> struct Store<PREC_BF16> {
   typedef uint16_t type;
-  static __device__ __forceinline__ void put(void* p, int64_t i, double v) {
+  static __host__ __device__ inline void put(void* p, int64_t i, double v) {
     ((uint16_t*)p)[i] = f32_to_bf16((float)v);
   }
-  static __device__ __forceinline__ double get(const void* p, int64_t i) {
+  static __host__ __device__ inline double get(const void* p, int64_t i) {
     return bf16_to_f32(((const uint16_t*)p)[i]);
   }
 };
