@@ -74,6 +74,17 @@ def config2() -> Problem:
     return euler_vortex(32, 4)
 
 
+def euler_vortex_tiled(n: int = 512, p: int = 4, perturb: float = 0.2, seed: int = 0) -> Problem:
+    """The vortex workload scaled up for a bandwidth measurement: n x n perturbed quads of the same
+    size as the 32 x 32 one (h = 10/32) on [0, 10 n / 32]^2, with the vortex repeated in every
+    10 x 10 tile (periodic), p = 4: 26.2 M unknowns at n = 512."""
+    L = 10.0 * n / 32
+    mesh = quad_mesh(n, n, p, box=((0.0, L), (0.0, L)), periodic=(True, True), perturb=perturb, seed=seed,
+                     name=f"vortex-tiled{n}x{n}p{p}")
+    U0 = fields.vortex(mesh, 0.0, beta=5.0, center=(5.0, 5.0), period=(10.0, 10.0))
+    return Problem(mesh.name, mesh, EQ_EULER, 4, U0, gamma=1.4, dt=2e-3, extra=dict(period=(L, L)))
+
+
 def taylor_green(n: int, p: int, re: float, mach: float = 0.2, dt: float = 0.05,
                  perturb_amp: float = 0.0, seed: int | None = None) -> Problem:
     mesh = hex_mesh(n, p, name=f"tgv{n}^3p{p}")
