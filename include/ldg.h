@@ -76,7 +76,13 @@ typedef struct {
   double c11_dirichlet;   /* LDG penalty C11 on Dirichlet faces (> 0 if any)     */
   int64_t n_elem;         /* E >= 1                                              */
   const double* node_xyz_host;    /* [E][D][Np] physical node coordinates           */
-  const int64_t* face_nbr_host;   /* [E][2D] neighbour element, or -(tag+1): tag 0 = Dirichlet */
+  const int64_t* face_nbr_host;   /* [E][2D] neighbour element, or -(kind+1) for a boundary face:
+                                     kind 0 Dirichlet (eqs. dirichlet1/2; for the inviscid flux
+                                     Roe(g_D, u_in), the characteristic condition), 1 Neumann
+                                     (eqs. neumann1/2 with C22 = 0: Fhat . n = |n| g_N,
+                                     uhat = u_in), 2 slip wall (Euler / Navier-Stokes:
+                                     Roe(u_m, u_in) with the mirror state u_m, normal momentum
+                                     reversed; no viscous flux through the wall; uhat = u_in) */
   const int32_t* nbr_node_host;   /* [E][2D][Nf] local node index, inside the neighbour, of
                                      the node that coincides with each face node      */
   const int8_t* switch_plus_host; /* [E][D] S^+_n                                     */
@@ -87,8 +93,9 @@ typedef struct {
  * mass matrix, its inverse folded into the lifting and test-derivative
  * operators).  hip_stream may be NULL (default stream).
  * Errors: LDG_E_INVALID / LDG_E_SHAPE (inconsistent connectivity, non-matching
- * switch signs, non-positive J is reported later as LDG_E_NONFINITE),
- * LDG_E_UNSUPPORTED (dim/p/equation outside the built set). */
+ * switch signs, a slip wall with the Poisson equation; non-positive J is
+ * reported later as LDG_E_NONFINITE), LDG_E_UNSUPPORTED (dim/p/equation or
+ * boundary kind outside the built set). */
 ldg_status ldg_create(const ldg_problem_desc* desc, void* hip_stream, ldg_ctx* out);
 void ldg_destroy(ldg_ctx ctx);
 
@@ -97,6 +104,11 @@ ldg_status ldg_set_source(ldg_ctx ctx, const double* S_dev);
 /* Dirichlet data g_D at boundary face nodes (eqs. dirichlet1/2); gD_dev
  * [E][2D][m][Nf] (only boundary faces are read), copied.  NULL = zero data. */
 ldg_status ldg_set_dirichlet(ldg_ctx ctx, const double* gD_dev);
+
+/* Neumann data g_N at boundary face nodes (eqs. neumann1/2: the prescribed
+ * normal flux F . nhat, unit outward normal); gN_dev [E][2D][m][Nf] (only
+ * Neumann faces are read), copied.  NULL = zero data. */
+ldg_status ldg_set_neumann(ldg_ctx ctx, const double* gN_dev);
 
 /* Q = D(U): the LDG gradient (eqs. splitdisc2, numfluxu1, semidisc2-2) with
  * the switch-selected traces; homogeneous != 0 uses g_D = 0 (then Q = K21 U).

@@ -36,6 +36,7 @@ class Problem:
     c11_dirichlet: float = 10.0
     source: np.ndarray | None = None
     gD: np.ndarray | None = None
+    gN: np.ndarray | None = None
     dt: float = 0.0
     extra: dict = dataclasses.field(default_factory=dict)
 

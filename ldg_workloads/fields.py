@@ -26,6 +26,18 @@ def face_values(mesh: Mesh, vol: np.ndarray) -> np.ndarray:
     return np.ascontiguousarray(np.transpose(vol[:, :, tab], (0, 2, 1, 3)))
 
 
+def axis_normal_face_values(mesh: Mesh, grad: np.ndarray) -> np.ndarray:
+    """grad . nhat at face nodes [E, 2D, m, Nf] for axis-aligned faces: face 2n+s has outward unit
+    normal (2s - 1) e_n (rectangular elements).  grad is [E, m, D, Np]."""
+    tab = face_node_table(mesh)
+    E, m, D = grad.shape[0], grad.shape[1], mesh.dim
+    out = np.empty((E, 2 * D, m, tab.shape[1]))
+    for f in range(2 * D):
+        n, s = divmod(f, 2)
+        out[:, f] = (2 * s - 1) * grad[:, :, n, tab[f]]
+    return out
+
+
 # ---------------------------------------------------------------- Poisson
 def poisson_sine(mesh: Mesh):
     """u = sin(pi x) sin(pi y), f = 2 pi^2 u (so that -Lap u = f)."""

@@ -280,3 +280,18 @@ def reorient_elements(mesh: Mesh, flips: np.ndarray, perm: np.ndarray | None = N
                         old_nb_node = mesh.nbr_node[e, fo, lo]
                         nbr_node[ne, fn, l] = old_to_new[nb, old_nb_node]
     return Mesh(dim, p, xyz, face_nbr, nbr_node, sw, name=mesh.name + "+relabelled")
+
+
+# boundary kinds of a face: face_nbr = -(kind + 1)
+BC_DIRICHLET, BC_NEUMANN, BC_SLIP = 0, 1, 2
+
+
+def with_boundary_kinds(mesh: Mesh, kinds: dict) -> Mesh:
+    """Copy of a structured mesh whose boundary faces carry the kind ``kinds[f]`` by local face
+    index f = 2n + s (the side xi_n = s of the box for meshes built here); faces not listed
+    stay Dirichlet."""
+    fn = mesh.face_nbr.copy()
+    for f, k in kinds.items():
+        col = fn[:, f]
+        col[col < 0] = -(int(k) + 1)
+    return Mesh(mesh.dim, mesh.p, mesh.xyz, fn, mesh.nbr_node, mesh.switch_plus, name=mesh.name)

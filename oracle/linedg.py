@@ -19,7 +19,13 @@ What is computed, and where the paper defines it:
   face switch is +1 and from the inside when it is -1, uhat the other way
   round; interior penalty C11 |n| (u_in - u_out); Dirichlet faces use
   Fhat = F(u_in, q_in).n + C11_D |n| (u_in - g_D), uhat = g_D (eqs.
-  dirichlet1/2); inviscid Dirichlet faces take Roe(g_D, u_in);
+  dirichlet1/2); inviscid Dirichlet faces take Roe(g_D, u_in) (the
+  characteristic far-field condition);
+* Neumann faces (eqs. neumann1/2 with C22 = 0): Fhat . n = |n| g_N, uhat = u_in;
+* slip walls: Roe(u_m, u_in) with the mirror state u_m (normal momentum
+  reflected), no viscous flux through the wall, uhat = u_in;
+  boundary kinds come from face_nbr = -(kind + 1): 0 Dirichlet, 1 Neumann,
+  2 slip wall;
 * Jacobians K11 = dR/dU, K12 = dR/dQ, K21 = dD/dU (Section 4.1), obtained by
   forward-mode differentiation of each line's right-hand side.
 
@@ -51,7 +57,7 @@ class LineDG:
     """The discrete operator for one mesh and one equation set."""
 
     def __init__(self, dim, p, xyz, face_nbr, nbr_node, switch_plus, physics: Physics,
-                 c11_interior=0.0, c11_dirichlet=10.0, source=None, gD=None, nodes="gll"):
+                 c11_interior=0.0, c11_dirichlet=10.0, source=None, gD=None, nodes="gll", gN=None):
         self.D = dim
         self.p = p
         self.n1 = p + 1
@@ -75,6 +81,7 @@ class LineDG:
         self.c11_dir = float(c11_dirichlet)
         self.source = None if source is None else _t(source)
         self.gD = None if gD is None else _t(gD)
+        self.gN = None if gN is None else _t(gN)
         self.nslot_line = dim * p + 1
         self.nslot11 = self.nslot_line + 2 * dim
         self.nslot12 = self.nslot_line + dim
@@ -169,6 +176,16 @@ class LineDG:
             return torch.zeros(len(elems), self.NL, self.m, dtype=DT)
         return self.gD[elems, 2 * n + s].permute(0, 2, 1)  # [Ne, NL, m]
 
+    def _gN_face(self, elems, n, s):
+        if self.gN is None:
+            return torch.zeros(len(elems), self.NL, self.m, dtype=DT)
+        return self.gN[elems, 2 * n + s].permute(0, 2, 1)  # [Ne, NL, m]
+
+    def _kind(self, elems, n, s):
+        """Boundary kind of face 2n+s per element: -1 interior, 0 Dirichlet, 1 Neumann, 2 slip wall."""
+        nb = self.face_nbr[elems, 2 * n + s]
+        return torch.where(nb >= 0, torch.full_like(nb, -1), -nb - 1)
+
     # ------------------------------------------------------------------ line problems
     def _mass_solve(self, b):
         """Solve M r = b along axis -3 (b: [..., N1, a, b'])."""
@@ -189,10 +206,12 @@ class LineDG:
                 + ep[:, None, None] * (uh1[..., :, None] * n1[..., None, :])[..., None, :, :])
         return face - vol
 
-    def _uhat(self, u_in, u_out, S, bnd, gD):
-        """LDG trace: inside if S = +1, outside if S = -1; g_D on Dirichlet faces."""
+    def _uhat(self, u_in, u_out, S, kind, gD):
+        """LDG trace: inside if S = +1, outside if S = -1; g_D on Dirichlet faces; the inside
+        value on Neumann faces (C22 = 0) and slip walls."""
         sel = torch.where((S > 0)[..., None], u_in, u_out)
-        return torch.where(bnd[..., None], gD, sel)
+        sel = torch.where((kind > 0)[..., None], u_in, sel)
+        return torch.where((kind == 0)[..., None], gD, sel)
 
     def gradient(self, U, elems=None, homogeneous=False, geo=None):
         """Q = D(U) for the given elements: [Ne, m, D, Np] (eqs. semidisc2-2)."""
@@ -213,38 +232,51 @@ class LineDG:
                 gD = torch.zeros_like(uo) if homogeneous else self._gD_face(elems, n, s)
                 S = Sp if s == 1 else -Sp
                 uin = ul[:, :, self.p if s == 1 else 0]
-                uh.append(self._uhat(uin, uo, S, bnd[:, None].expand(Ne, self.NL), gD))
+                kind = self._kind(elems, n, s)[:, None].expand(Ne, self.NL)
+                uh.append(self._uhat(uin, uo, S, kind, gD))
             b = self.grad_line_rhs(ul, uh[0], uh[1], geo["ag"][n], geo["n0"][n], geo["n1"][n])
             d = self._mass_solve(b)  # [Ne, NL, N1, m, D]
             acc += self.from_lines(d.reshape(Ne, self.NL, self.n1, self.m * self.D), n).reshape(
                 Ne, self.m, self.D, self.Np)
         return acc / geo["J"][:, None, None, :]
 
-    def face_flux(self, u_in, q_in, u_out, q_out, nrm, S, bnd, gD):
-        """Numerical flux Fhat . n at one face point (shapes [..., m])."""
+    @staticmethod
+    def mirror(u, nrm):
+        """The wall's mirror state: normal momentum reversed, density and energy kept."""
+        nb = nrm / torch.sqrt((nrm * nrm).sum(-1, keepdim=True))
+        D = nrm.shape[-1]
+        mom = u[..., 1:1 + D]
+        mn = (mom * nb).sum(-1, keepdim=True)
+        return torch.cat([u[..., :1], mom - 2.0 * mn * nb, u[..., 1 + D:]], dim=-1)
+
+    def face_flux(self, u_in, q_in, u_out, q_out, nrm, S, kind, gD, gN):
+        """Numerical flux Fhat . n at one face point (shapes [..., m]); kind -1 interior,
+        0 Dirichlet, 1 Neumann, 2 slip wall."""
         ph = self.ph
+        nn = torch.sqrt((nrm * nrm).sum(-1))[..., None]
         out = torch.zeros_like(u_in)
+        dirichlet, slip = (kind == 0)[..., None], (kind == 2)[..., None]
         if ph.has_inviscid:
-            uR = torch.where(bnd[..., None], gD, u_out)
+            uR = torch.where(dirichlet, gD, torch.where(slip, self.mirror(u_in, nrm), u_out))
             out = out + ph.roe_flux(uR, u_in, nrm)
         if ph.has_viscous:
-            nn = torch.sqrt((nrm * nrm).sum(-1))[..., None]
             Fin = (ph.flux_vis(u_in, q_in) * nrm[..., None, :]).sum(-1)
             Fout = (ph.flux_vis(u_out, q_out) * nrm[..., None, :]).sum(-1)
             interior = torch.where((S > 0)[..., None], Fout, Fin) + self.c11_int * nn * (u_in - u_out)
             dirich = Fin + self.c11_dir * nn * (u_in - gD)
-            out = out + torch.where(bnd[..., None], dirich, interior)
-        return out
+            vis = torch.where(dirichlet, dirich, interior)
+            out = out + torch.where(slip, torch.zeros_like(vis), vis)
+        return torch.where((kind == 1)[..., None], nn * gN, out)
 
-    def resid_line_rhs(self, u_line, q_line, uo0, qo0, uo1, qo1, ag, n0, n1, S1, bnd0, bnd1, gD0, gD1):
+    def resid_line_rhs(self, u_line, q_line, uo0, qo0, uo1, qo1, ag, n0, n1, S1, k0, k1, gD0, gD1, gN0, gN1):
         """Right-hand side b[.., i, c] of the line problem for r^(n) (eq. galerkinscheme2)."""
         ug = torch.einsum("gi,...ic->...gc", self.I, u_line)
         qg = torch.einsum("gi,...icd->...gcd", self.I, q_line)
         Fg = self.ph.flux_total(ug, qg)
         ft = (Fg * ag[..., None, :]).sum(-1)  # [..., ng, m]
         vol = torch.einsum("g,gi,...gc->...ic", self.wg, self.Dg, ft)
-        F1 = self.face_flux(u_line[..., self.p, :], q_line[..., self.p, :, :], uo1, qo1, n1, S1, bnd1, gD1)
-        F0 = self.face_flux(u_line[..., 0, :], q_line[..., 0, :, :], uo0, qo0, n0, -S1, bnd0, gD0)
+        F1 = self.face_flux(u_line[..., self.p, :], q_line[..., self.p, :, :], uo1, qo1, n1, S1, k1, gD1, gN1)
+        F0 = self.face_flux(u_line[..., 0, :], q_line[..., 0, :, :], uo0, qo0, n0, -S1, k0, gD0, gN0)
         e0 = torch.zeros(self.n1, dtype=DT)
         e0[0] = 1.0
         ep = torch.zeros(self.n1, dtype=DT)
@@ -272,7 +304,9 @@ class LineDG:
             qo = Q[rows[:, None], :, :, ndc]  # [Ne, NL, m, D]
             qo = torch.where((nb < 0)[:, None, None, None], torch.zeros_like(qo), qo)
             gD = self._gD_face(elems, n, s)
-            outs.append((uo, qo, bnd[:, None].expand(Ne, self.NL), gD))
+            gN = self._gN_face(elems, n, s)
+            kind = self._kind(elems, n, s)[:, None].expand(Ne, self.NL)
+            outs.append((uo, qo, kind, gD, gN))
         S1 = self.switch_plus[elems, n][:, None].expand(Ne, self.NL)
         return ul, ql, outs, S1
 
@@ -301,9 +335,9 @@ class LineDG:
         acc_abs = torch.zeros(Ne, self.m, self.Np, dtype=DT)
         for n in range(self.D):
             ul, ql, outs, S1 = self._line_inputs(U, Q, elems, n, qidx)
-            (uo0, qo0, b0, g0), (uo1, qo1, b1, g1) = outs
+            (uo0, qo0, b0, g0, h0), (uo1, qo1, b1, g1, h1) = outs
             b = self.resid_line_rhs(ul, ql, uo0, qo0, uo1, qo1, geo["ag"][n], geo["n0"][n], geo["n1"][n],
-                                    S1, b0, b1, g0, g1)
+                                    S1, b0, b1, g0, g1, h0, h1)
             r = torch.cholesky_solve(b, self.Mchol)  # [Ne, NL, N1, m]
             rn = self.from_lines(r, n)
             acc += rn
@@ -369,10 +403,10 @@ class LineDG:
         ar_e = torch.arange(Ne)
         for n in range(D):
             ul, ql, outs, S1 = self._line_inputs(U, Q, elems, n, qidx)
-            (uo0, qo0, b0, g0), (uo1, qo1, b1, g1) = outs
+            (uo0, qo0, b0, g0, h0), (uo1, qo1, b1, g1, h1) = outs
             flat = lambda t: t.reshape((Ne * NL,) + t.shape[2:])
             args = [flat(x) for x in (ul, ql, uo0, qo0, uo1, qo1, geo["ag"][n], geo["n0"][n], geo["n1"][n],
-                                      S1, b0, b1, g0, g1)]
+                                      S1, b0, b1, g0, g1, h0, h1)]
             jf = vmap(jacfwd(self.resid_line_rhs, argnums=(0, 1, 2, 3, 4, 5)))
             jb = jf(*args)
             # solve with M along the row-position axis (axis 1 after the batch)
@@ -394,8 +428,8 @@ class LineDG:
                         K11[:, a, sl] += sc[:, l, i] * d_ul[:, l, i, :, t, :]
                         K12[:, a, sl] += sc[:, l, i] * d_ql[:, l, i, :, t, :, :].reshape(Ne, m, m * D)
                     base = self.nslot_line
-                    for s, (duo, dqo, bnd) in enumerate(((d_uo0, d_qo0, b0), (d_uo1, d_qo1, b1))):
-                        keep = (~bnd[:, l]).to(DT)[:, None, None]
+                    for s, (duo, dqo, kd) in enumerate(((d_uo0, d_qo0, b0), (d_uo1, d_qo1, b1))):
+                        keep = (kd[:, l] < 0).to(DT)[:, None, None]
                         K11[:, a, base + 2 * n + s] += keep * sc[:, l, i] * duo[:, l, i]
                         # K12 neighbour slot: the side whose switch is +1
                         side_plus = torch.where(Sp > 0, 1, 0)
@@ -415,15 +449,16 @@ class LineDG:
         ag, n0, n1v = geo["ag"][n], geo["n0"][n], geo["n1"][n]
         J = geo["J"]
         eye = torch.eye(n1, dtype=DT)
-        bnd0 = (self.face_nbr[elems, 2 * n] < 0)[:, None, None]
-        bnd1 = (self.face_nbr[elems, 2 * n + 1] < 0)[:, None, None]
+        k0 = self._kind(elems, n, 0)[:, None, None]
+        k1 = self._kind(elems, n, 1)[:, None, None]
         for t in range(n1):
             ul = eye[t][None, None, :, None].expand(Ne, NL, n1, 1)
             zero = torch.zeros(Ne, NL, 1, dtype=DT)
             uin0, uin1 = ul[:, :, 0], ul[:, :, p]
-            # uhat: inside where the face switch is +1 (g_D on Dirichlet faces)
-            uh1 = torch.where((Sp > 0)[:, None, None] & ~bnd1, uin1, zero)
-            uh0 = torch.where((Sp < 0)[:, None, None] & ~bnd0, uin0, zero)
+            # uhat: inside where the face switch is +1 on interior faces and on Neumann / slip
+            # faces (g_D, which does not depend on U, on Dirichlet faces)
+            uh1 = torch.where(((Sp > 0)[:, None, None] & (k1 < 0)) | (k1 > 0), uin1, zero)
+            uh0 = torch.where(((Sp < 0)[:, None, None] & (k0 < 0)) | (k0 > 0), uin0, zero)
             b = self.grad_line_rhs(ul, uh0, uh1, ag, n0, n1v)
             d = self._mass_solve(b)[..., 0, :]  # [Ne, NL, N1, D]
             for l in range(NL):

@@ -225,6 +225,7 @@ __global__ void __launch_bounds__(NT_ELEM) jac_kernel(LineOps ops_arg, MeshParam
         for (int d = 0; d < D; ++d) nrm[d] = s ? an[d] : -an[d];
         const int f = 2 * n + s;
         const int64_t nb = mp.face_nbr[e * 2 * D + f];
+        const int kind = face_kind(nb);
         const bool bnd = nb < 0;
         const int Sp = mp.sw[e * D + n];
         const int S = s ? Sp : -Sp;
@@ -237,8 +238,9 @@ __global__ void __launch_bounds__(NT_ELEM) jac_kernel(LineOps ops_arg, MeshParam
 #pragma unroll
           for (int c = 0; c < M; ++c) uout[c] = U[(nb * M + c) * NP + nd];
         } else {
+          const double* gb = kind == BC_NEUMANN ? mp.gN : mp.gD;
 #pragma unroll
-          for (int c = 0; c < M; ++c) uout[c] = mp.gD ? mp.gD[((e * 2 * D + f) * M + c) * NL + l] : 0.0;
+          for (int c = 0; c < M; ++c) uout[c] = gb ? gb[((e * 2 * D + f) * M + c) * NL + l] : 0.0;
         }
         if constexpr (VIS) {
           if (part == 0) {  // the gradient derivatives do not involve q itself
@@ -274,13 +276,14 @@ __global__ void __launch_bounds__(NT_ELEM) jac_kernel(LineOps ops_arg, MeshParam
                 ti[c].d[0] = side == 0 ? seed : 0.0;
                 to[c].d[0] = side == 0 ? 0.0 : seed;
               }
-              face_flux_point<D, EQ, T1, true, double>(ti, to, qs, nrm, S, bnd, mp, F);
+              face_flux_point<D, EQ, T1, true, double>(ti, to, qs, nrm, S, kind, mp, F);
 #pragma unroll
               for (int c = 0; c < M; ++c) dst[c * M + k] = F[c].d[0];
             }
           } else if constexpr (VIS) {
-            // only the selected side's gradient enters the flux, linearly
-            if ((side == 1) != use_out) {
+            // only the selected side's gradient enters the flux, linearly (and none on
+            // Neumann faces and slip walls)
+            if ((side == 1) != use_out || kind == BC_NEUMANN || kind == BC_SLIP) {
 #pragma unroll
               for (int k = 0; k < M * M; ++k) dst[k] = 0.0;
               continue;

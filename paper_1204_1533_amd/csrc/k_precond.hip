@@ -245,10 +245,12 @@ __global__ void __launch_bounds__(NT_ELEM) form_kernel(LineOps ops, MeshParams m
       double v = 0.0;
 #pragma unroll
       for (int g = 0; g < NG; ++g) v -= ops.V[t][g] * ops.I[g][tp] * sAg[((n * NL + l) * NG + g) * D + d];
+      // the trace is taken inside: switch +1 on an interior face, or a Neumann face / slip wall
       const int Sp = mp.sw[e * D + n];
-      if (tp == P && Sp > 0 && mp.face_nbr[e * 2 * D + 2 * n + 1] >= 0)
+      const int k1 = face_kind(mp.face_nbr[e * 2 * D + 2 * n + 1]), k0 = face_kind(mp.face_nbr[e * 2 * D + 2 * n]);
+      if (tp == P && ((Sp > 0 && k1 == BC_INTERIOR) || k1 == BC_NEUMANN || k1 == BC_SLIP))
         v += ops.L1[t] * sN[((n * NL + l) * 2 + 1) * D + d];
-      if (tp == 0 && Sp < 0 && mp.face_nbr[e * 2 * D + 2 * n] >= 0)
+      if (tp == 0 && ((Sp < 0 && k0 == BC_INTERIOR) || k0 == BC_NEUMANN || k0 == BC_SLIP))
         v += ops.L0[t] * sN[((n * NL + l) * 2 + 0) * D + d];
       sW[it] = v;
     }

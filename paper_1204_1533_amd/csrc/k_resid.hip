@@ -10,7 +10,8 @@
 //     a_n = J G^{-T} N_n (eq. contraflux) and the contravariant flux F . a_n;
 //   * face phase (one work item per line end): the point flux at the face
 //     node with the coinciding node of the neighbour (Riemann + LDG switch,
-//     Section 3), or the Dirichlet flux (eqs. dirichlet1/2);
+//     Section 3), or the boundary flux of the face's kind (Dirichlet,
+//     Neumann, slip wall);
 //   * projection (one work item per node and component): the 1-D Galerkin
 //     solution r_i = L1_i Fhat^+ + L0_i Fhat^- - sum_g V_ig f~_g of eq.
 //     galerkinscheme2 with the mass solve folded into L0, L1, V, summed over
@@ -203,34 +204,36 @@ __global__ void __launch_bounds__(NT_ELEM) resid_kernel(LineOps ops, MeshParams 
       for (int d = 0; d < D; ++d) nrm[d] = s ? an[d] : -an[d];
       const int f = 2 * n + s;
       const int64_t nb = mp.face_nbr[eg * 2 * D + f];
-      const bool bnd = nb < 0;
+      const int kind = face_kind(nb);
       T uin[M], uout[M];
 #pragma unroll
       for (int c = 0; c < M; ++c) uin[c] = sU[(e * M + c) * NP + nin];
       int nd = 0;
-      if (!bnd) {
+      if (kind == BC_INTERIOR) {
         nd = mp.nbr_node[(eg * 2 * D + f) * NL + l];
 #pragma unroll
         for (int c = 0; c < M; ++c) uout[c] = IO<T>::load(U, Ut, (nb * M + c) * NP + nd);
       } else {
+        // boundary data of the face's kind (unused on slip walls)
+        const double* gb = kind == BC_NEUMANN ? mp.gN : mp.gD;
 #pragma unroll
-        for (int c = 0; c < M; ++c) uout[c] = cst<T>(mp.gD ? mp.gD[((eg * 2 * D + f) * M + c) * NL + l] : 0.0);
+        for (int c = 0; c < M; ++c) uout[c] = cst<T>(gb ? gb[((eg * 2 * D + f) * M + c) * NL + l] : 0.0);
       }
       T F[M];
       if constexpr (VIS) {
         const int Sp = mp.sw[eg * D + n];
         const int S = s ? Sp : -Sp;
         T qsel[M * D];
-        if (!bnd && S > 0) {
+        if (kind == BC_INTERIOR && S > 0) {
 #pragma unroll
           for (int c = 0; c < M * D; ++c) qsel[c] = IO<T>::load(Q, Qt, (nb * QW + c) * NP + nd);
         } else {
 #pragma unroll
           for (int c = 0; c < M * D; ++c) qsel[c] = sQ[(e * QW + c) * NP + nin];
         }
-        face_flux_point<D, EQ, T>(uin, uout, qsel, nrm, S, bnd, mp, F);
+        face_flux_point<D, EQ, T>(uin, uout, qsel, nrm, S, kind, mp, F);
       } else {
-        face_flux_point<D, EQ, T>(uin, uout, uin, nrm, 1, bnd, mp, F);
+        face_flux_point<D, EQ, T>(uin, uout, uin, nrm, 1, kind, mp, F);
       }
 #pragma unroll
       for (int c = 0; c < M; ++c) sH[i * M + c] = F[c];
@@ -357,13 +360,15 @@ __global__ void __launch_bounds__(NT_ELEM) grad_kernel(LineOps ops, MeshParams m
       for (int d = 0; d < D; ++d) sNh[i * D + d] = s ? an[d] : -an[d];
       const int f = 2 * n + s;
       const int64_t nb = mp.face_nbr[eg * 2 * D + f];
+      const int kind = face_kind(nb);
       const int Sp = mp.sw[eg * D + n];
       const int S = s ? Sp : -Sp;
-      if (nb < 0) {
+      if (kind == BC_DIRICHLET) {
 #pragma unroll
         for (int c = 0; c < M; ++c)
           sUh[i * M + c] = (homogeneous || !mp.gD) ? 0.0 : mp.gD[((eg * 2 * D + f) * M + c) * NL + l];
-      } else if (S > 0) {
+      } else if (kind != BC_INTERIOR || S > 0) {
+        // the inside trace: switch +1, or a Neumann face / slip wall
 #pragma unroll
         for (int c = 0; c < M; ++c) sUh[i * M + c] = sU[(e * M + c) * NP + nin];
       } else {

@@ -20,6 +20,7 @@ struct ldg_ctx_s {
   int32_t* d_nbr_node = nullptr;
   int8_t* d_sw = nullptr;
   double* d_gD = nullptr;
+  double* d_gN = nullptr;
   double* d_S = nullptr;
   double* d_Q = nullptr;   // Q scratch (residual)
   double* d_W = nullptr;   // K21 x scratch
@@ -72,6 +73,7 @@ struct ldg_ctx_s {
   const double* rk_U = nullptr;
   const double* rk_S = nullptr;
   const double* rk_gD = nullptr;
+  const double* rk_gN = nullptr;
   double rk_dt = 0.0;
   // learned correction of the preconditioner
   ldg_net net = nullptr;         // attached network (owned by the caller)

@@ -51,8 +51,15 @@ struct MeshParams {
   const int32_t* nbr_node; // [E][2D][Nf]
   const int8_t* sw;        // [E][D]
   const double* gD;        // [E][2D][m][Nf] or null
+  const double* gN;        // [E][2D][m][Nf] or null
   const double* S;         // [E][m][Np] or null
 };
+
+// Kind of a face from its face_nbr entry: a neighbour (interior) or a boundary
+// -(kind + 1): Dirichlet (eqs. dirichlet1/2; inviscid: the characteristic
+// condition Roe(g_D, u_in)), Neumann (eqs. neumann1/2 with C22 = 0), slip wall.
+constexpr int BC_INTERIOR = -1, BC_DIRICHLET = 0, BC_NEUMANN = 1, BC_SLIP = 2;
+__host__ __device__ inline int face_kind(int64_t nb) { return nb >= 0 ? BC_INTERIOR : (int)(-nb - 1); }
 
 // ---------------------------------------------------------------- node indexing
 // node(n, l, t): position t on line l of direction n.
@@ -401,62 +408,69 @@ __host__ __device__ inline double det(const double G[D][D]) {
 }  // namespace ldg
 
 namespace ldg {
-// Point flux Fhat . n at one face node (Sections 2.2 and 3):
-//   inviscid  Roe(u_out, u_in; n) (Roe(g_D, u_in; n) on a Dirichlet face);
-//   viscous   F^vis of the outside state when the face switch S is +1, of the
-//             inside state when S = -1, dotted with n, plus C11 |n| (u_in - u_out);
-//             on a Dirichlet face F^vis(u_in, q_in) . n + C11_D |n| (u_in - g_D)
-//             (u_out holds g_D there).
+// Mirror state across a wall with normal n: normal momentum reversed, density
+// and energy kept (the outside state of a slip wall).
+template <int D, class T>
+__device__ __forceinline__ void mirror_state(const T* u, const double* n, T* r) {
+  double nn2 = 0.0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) nn2 += n[d] * n[d];
+  const double inv = 1.0 / sqrt(nn2);
+  T mn = cst<T>(0.0);
+#pragma unroll
+  for (int d = 0; d < D; ++d) mn += u[1 + d] * (n[d] * inv);
+  r[0] = u[0];
+#pragma unroll
+  for (int d = 0; d < D; ++d) r[1 + d] = u[1 + d] - (2.0 * n[d] * inv) * mn;
+  r[D + 1] = u[D + 1];
+}
+
+// Point flux Fhat . n at one face node (Sections 2.2 and 3), by face kind:
+//   interior   inviscid Roe(u_out, u_in; n); viscous F^vis of the outside state
+//              when the face switch S is +1, of the inside state when S = -1,
+//              dotted with n, plus C11 |n| (u_in - u_out);
+//   Dirichlet  Roe(g_D, u_in; n) + F^vis(u_in, q_in) . n + C11_D |n| (u_in - g_D)
+//              (u_out holds g_D);
+//   Neumann    |n| g_N (u_out holds g_N), independent of u and q;
+//   slip wall  Roe(u_m, u_in; n) with the mirror state u_m, no viscous flux.
 // qsel is the gradient of the side whose viscous flux is taken: the outside
 // for an interior face with S = +1, the inside otherwise.  The viscous part is
 // evaluated first so the gradient is dead before the Riemann solve.
 template <int D, int EQ, class T, bool WITH_INV = true, class TQ = T>
 __device__ __forceinline__ void face_flux_point(const T* uin, const T* uout, const TQ* qsel, const double* nrm,
-                                                int S, bool bnd, const MeshParams& mp, T* F) {
+                                                int S, int kind, const MeshParams& mp, T* F) {
   constexpr int M = Eq<D, EQ>::M;
+  double nn = 0.0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) nn += nrm[d] * nrm[d];
+  nn = sqrt(nn);
 #pragma unroll
   for (int c = 0; c < M; ++c) F[c] = cst<T>(0.0);
+  if (kind == BC_NEUMANN) {
+#pragma unroll
+    for (int c = 0; c < M; ++c) F[c] = nn * uout[c];
+    return;
+  }
   if constexpr (Eq<D, EQ>::VIS) {
-    double nn = 0.0;
+    if (kind != BC_SLIP) {
+      const bool use_out = kind == BC_INTERIOR && S > 0;
+      visc_flux_dot_add<D, EQ, T, TQ>(use_out ? uout : uin, qsel, nrm, mp.gamma, mp.mu, mp.prandtl, F);
+      const double c11 = kind == BC_DIRICHLET ? mp.c11d : mp.c11i;
 #pragma unroll
-    for (int d = 0; d < D; ++d) nn += nrm[d] * nrm[d];
-    nn = sqrt(nn);
-    const bool use_out = !bnd && S > 0;
-    visc_flux_dot_add<D, EQ, T, TQ>(use_out ? uout : uin, qsel, nrm, mp.gamma, mp.mu, mp.prandtl, F);
-    const double c11 = bnd ? mp.c11d : mp.c11i;
-#pragma unroll
-    for (int c = 0; c < M; ++c) F[c] += (c11 * nn) * (uin[c] - uout[c]);
+      for (int c = 0; c < M; ++c) F[c] += (c11 * nn) * (uin[c] - uout[c]);
+    }
   }
   if constexpr (Eq<D, EQ>::INV && WITH_INV) {
     T Fr[M];
-    roe_flux<D, T>(uout, uin, nrm, mp.gamma, Fr);
+    if (kind == BC_SLIP) {
+      T um[M];
+      mirror_state<D, T>(uin, nrm, um);
+      roe_flux<D, T>(um, uin, nrm, mp.gamma, Fr);
+    } else {
+      roe_flux<D, T>(uout, uin, nrm, mp.gamma, Fr);
+    }
 #pragma unroll
     for (int c = 0; c < M; ++c) F[c] += Fr[c];
-  }
-}
-
-// Same point flux with both sides' gradients given (the assembly kernel's
-// form): qin is the inside gradient, qout the outside one.
-template <int D, int EQ, class T, bool WITH_INV = true>
-__device__ __forceinline__ void face_flux_point_io(const T* uin, const T* qin, const T* uout, const T* qout,
-                                                   const double* nrm, int S, bool bnd, const MeshParams& mp, T* F) {
-  constexpr int M = Eq<D, EQ>::M;
-#pragma unroll
-  for (int c = 0; c < M; ++c) F[c] = cst<T>(0.0);
-  if constexpr (Eq<D, EQ>::INV && WITH_INV) roe_flux<D, T>(uout, uin, nrm, mp.gamma, F);
-  if constexpr (Eq<D, EQ>::VIS) {
-    double nn = 0.0;
-#pragma unroll
-    for (int d = 0; d < D; ++d) nn += nrm[d] * nrm[d];
-    nn = sqrt(nn);
-    T fv[M];
-#pragma unroll
-    for (int c = 0; c < M; ++c) fv[c] = cst<T>(0.0);
-    const bool use_out = !bnd && S > 0;
-    visc_flux_dot_add<D, EQ, T>(use_out ? uout : uin, use_out ? qout : qin, nrm, mp.gamma, mp.mu, mp.prandtl, fv);
-    const double c11 = bnd ? mp.c11d : mp.c11i;
-#pragma unroll
-    for (int c = 0; c < M; ++c) F[c] += fv[c] + (c11 * nn) * (uin[c] - uout[c]);
   }
 }
 }  // namespace ldg

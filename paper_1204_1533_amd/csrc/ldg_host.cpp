@@ -73,7 +73,7 @@ int64_t ldg_num_dofs(ldg_ctx ctx) { return ctx ? ctx->ndof : -1; }
 
 void ldg_destroy(ldg_ctx c) {
   if (!c) return;
-  void* ptrs[] = {c->d_xyz, c->d_face_nbr, c->d_nbr_node, c->d_sw, c->d_gD, c->d_S, c->d_Q, c->d_W, c->d_W2,
+  void* ptrs[] = {c->d_xyz, c->d_face_nbr, c->d_nbr_node, c->d_sw, c->d_gD, c->d_gN, c->d_S, c->d_Q, c->d_W, c->d_W2,
                   c->d_K11, c->d_K12, c->d_F, c->d_Fem, c->d_Ua, c->d_Qa, c->d_V, c->d_Z, c->d_R, c->d_G, c->d_x, c->d_r, c->d_z,
                   c->d_tmp, c->d_Un, c->d_partial, c->d_h, c->d_Uold, c->d_st_Un, c->d_st_comb, c->d_st_K};
   for (void* p : ptrs)
@@ -131,8 +131,14 @@ ldg_status ldg_create(const ldg_problem_desc* d, void* stream, ldg_ctx* out) {
         const int64_t nb = d->face_nbr_host[e * 2 * D + f];
         if (nb >= E) return bad(LDG_E_SHAPE, std::string("face_nbr out of range") + " (element " + std::to_string(e) + ", face " + std::to_string(f) + ")");
         if (nb < 0) {
-          if (nb != -1) return bad(LDG_E_UNSUPPORTED, std::string("only boundary tag 0 (Dirichlet) is built") + " (element " + std::to_string(e) + ", face " + std::to_string(f) + ")");
-          any_dirichlet = true;
+          const int kind = face_kind(nb);
+          if (kind > BC_SLIP)
+            return bad(LDG_E_UNSUPPORTED, "boundary kinds are 0 (Dirichlet), 1 (Neumann), 2 (slip wall) (element " +
+                                              std::to_string(e) + ", face " + std::to_string(f) + ")");
+          if (kind == BC_SLIP && d->equation == LDG_POISSON)
+            return bad(LDG_E_INVALID, "a slip wall needs the Euler or Navier-Stokes equations (element " +
+                                          std::to_string(e) + ", face " + std::to_string(f) + ")");
+          if (kind == BC_DIRICHLET) any_dirichlet = true;
           continue;
         }
         for (int l = 0; l < NL; ++l) {
@@ -200,6 +206,7 @@ ldg_status ldg_create(const ldg_problem_desc* d, void* stream, ldg_ctx* out) {
   mp.nbr_node = c->d_nbr_node;
   mp.sw = c->d_sw;
   mp.gD = nullptr;
+  mp.gN = nullptr;
   mp.S = nullptr;
   *out = c;
   return LDG_OK;
@@ -227,6 +234,19 @@ ldg_status ldg_set_dirichlet(ldg_ctx c, const double* gD) {
   TRY(dev_alloc(c, &c->d_gD, n));
   HIPCK(c, hipMemcpyAsync(c->d_gD, gD, sizeof(double) * n, hipMemcpyDeviceToDevice, c->dc.stream));
   c->dc.mp.gD = c->d_gD;
+  return LDG_OK;
+}
+
+ldg_status ldg_set_neumann(ldg_ctx c, const double* gN) {
+  if (!c) return LDG_E_INVALID;
+  if (!gN) {
+    c->dc.mp.gN = nullptr;
+    return LDG_OK;
+  }
+  const size_t n = (size_t)c->dc.E * 2 * c->dc.D * c->dc.M * c->dc.NL;
+  TRY(dev_alloc(c, &c->d_gN, n));
+  HIPCK(c, hipMemcpyAsync(c->d_gN, gN, sizeof(double) * n, hipMemcpyDeviceToDevice, c->dc.stream));
+  c->dc.mp.gN = c->d_gN;
   return LDG_OK;
 }
 
@@ -804,8 +824,10 @@ ldg_status ldg_implicit_step(ldg_ctx c, double* U, double* Uprev, double dt, con
     r.newton_res_final = g;
     ++r.stages;
     if (all_ok && !conv) {
-      c->err = "stage " + std::to_string(st + 1) + ": ||G|| = " + std::to_string(g) + " after " +
-               std::to_string(k) + " Newton iterations, tolerance " + std::to_string(tol);
+      char buf[160];
+      std::snprintf(buf, sizeof(buf), "stage %d: ||G|| = %.3e after %d Newton iterations, tolerance %.3e", st + 1, g,
+                    k, tol);
+      c->err = buf;
       all_ok = false;
       break;
     }
@@ -871,7 +893,8 @@ ldg_status ldg_rk4(ldg_ctx c, double* U, double dt, int32_t nsteps) {
     HIPCK(c, hipEventCreateWithFlags(&c->rk_ev[1], hipEventDisableTiming));
   }
   // (re)capture one step when its kernel arguments change
-  if (!c->rk_exec || c->rk_U != U || c->rk_dt != dt || c->rk_S != c->dc.mp.S || c->rk_gD != c->dc.mp.gD) {
+  if (!c->rk_exec || c->rk_U != U || c->rk_dt != dt || c->rk_S != c->dc.mp.S || c->rk_gD != c->dc.mp.gD ||
+      c->rk_gN != c->dc.mp.gN) {
     rk4_drop_graph(c);
     const hipStream_t caller = c->dc.stream;
     c->dc.stream = c->rk_stream;
@@ -890,6 +913,7 @@ ldg_status ldg_rk4(ldg_ctx c, double* U, double dt, int32_t nsteps) {
     c->rk_dt = dt;
     c->rk_S = c->dc.mp.S;
     c->rk_gD = c->dc.mp.gD;
+    c->rk_gN = c->dc.mp.gN;
   }
   // caller's stream -> graph stream -> caller's stream
   HIPCK(c, hipEventRecord(c->rk_ev[0], c->dc.stream));

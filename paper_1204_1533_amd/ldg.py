@@ -91,6 +91,7 @@ _SIGS = {
     "ldg_destroy": (None, [_P]),
     "ldg_set_source": (ctypes.c_int, [_P, _P]),
     "ldg_set_dirichlet": (ctypes.c_int, [_P, _P]),
+    "ldg_set_neumann": (ctypes.c_int, [_P, _P]),
     "ldg_gradient": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32]),
     "ldg_residual": (ctypes.c_int, [_P, _P, _P, _P]),
     "ldg_jacobian_assemble": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_int32]),
@@ -216,6 +217,9 @@ class Context:
 
     def ldg_set_dirichlet(self, gD):
         self._check(self.lib.ldg_set_dirichlet(self.h, _ptr(gD)))
+
+    def ldg_set_neumann(self, gN):
+        self._check(self.lib.ldg_set_neumann(self.h, _ptr(gN)))
 
     def ldg_gradient(self, U, Q, homogeneous=False):
         self._check(self.lib.ldg_gradient(self.h, _ptr(U), _ptr(Q), int(homogeneous)))

@@ -10,7 +10,7 @@ def oracle_of(pr):
     me = pr.mesh
     ph = Physics(pr.equation, me.dim, gamma=pr.gamma, mu=pr.mu, prandtl=pr.prandtl)
     return LineDG(me.dim, me.p, me.xyz, me.face_nbr, me.nbr_node, me.switch_plus, ph,
-                  pr.c11_interior, pr.c11_dirichlet, pr.source, pr.gD)
+                  pr.c11_interior, pr.c11_dirichlet, pr.source, pr.gD, gN=pr.gN)
 
 
 def gpu_of(pr):
@@ -25,6 +25,9 @@ def gpu_of(pr):
     if pr.gD is not None:
         dev["gD"] = torch.as_tensor(pr.gD, device="cuda").contiguous()
         ctx.ldg_set_dirichlet(dev["gD"])
+    if pr.gN is not None:
+        dev["gN"] = torch.as_tensor(pr.gN, device="cuda").contiguous()
+        ctx.ldg_set_neumann(dev["gN"])
     ctx._dev = dev
     return ctx
 
@@ -77,7 +80,58 @@ def relabel_nodal(V, mesh, flips, perm):
     return out
 
 
+def poisson_mixed(p=3, n=3, dim=2):
+    """Poisson with Dirichlet faces xi_n = 0 and Neumann faces xi_n = 1 of the box (rectangular
+    elements), u in Q_p with its Dirichlet values and Neumann data -grad u . nhat."""
+    from ldg_workloads import BC_NEUMANN, with_boundary_kinds
+    if dim == 2:
+        base = quad_mesh(n, n, p, box=((0.2, 1.4), (-0.3, 0.9)))
+        u, f, g = fields.poisson_polynomial(base, degs=(p, p - 1))
+    else:
+        base = hex_mesh(n, p, length=1.0, periodic=False, amp=0.0)
+        u, f, g = fields.poisson_polynomial_3d(base, degs=(p, 1, p))
+    mesh = with_boundary_kinds(base, {2 * k + 1: BC_NEUMANN for k in range(dim)})
+    pr = configs.Problem(f"poisson{dim}d_mixed_n{n}p{p}", mesh, configs.EQ_POISSON, 1,
+                         u + 0.05 * np.sin(3.0 * mesh.xyz[:, 0:1]), source=f, gD=fields.face_values(mesh, u),
+                         gN=-fields.axis_normal_face_values(mesh, g), c11_dirichlet=10.0)
+    pr.extra["u_exact"] = u
+    return pr
+
+
+def channel_case(eq, p=3, seed=0):
+    """Periodic in x, slip walls at y = 0 and y = 2 on a perturbed mesh; a smooth random state."""
+    from ldg_workloads import BC_SLIP, with_boundary_kinds
+    base = quad_mesh(4, 3, p, box=((0, 4), (0, 2)), periodic=(True, False), perturb=0.2, seed=3)
+    mesh = with_boundary_kinds(base, {2: BC_SLIP, 3: BC_SLIP})
+    U = fields.random_smooth_state(mesh, 4, seed=seed + 1, base=[1.0, 0.3, -0.2, 2.6], amp=0.1)
+    return configs.Problem(f"channel_{'ns' if eq == configs.EQ_NS else 'euler'}_p{p}", mesh, eq, 4, U,
+                           mu=0.05 if eq == configs.EQ_NS else 0.0)
+
+
+def box_mixed_ns(p=2, seed=0):
+    """3-D Navier-Stokes on a non-periodic 2^3 box: Dirichlet faces x = 0, 1, slip walls y = 0, 1,
+    Neumann faces z = 0, 1 (data: a smooth field's face values, small)."""
+    from ldg_workloads import BC_NEUMANN, BC_SLIP, with_boundary_kinds
+    base = hex_mesh(2, p, length=1.0, periodic=False, amp=0.05)
+    mesh = with_boundary_kinds(base, {2: BC_SLIP, 3: BC_SLIP, 4: BC_NEUMANN, 5: BC_NEUMANN})
+    st = [1.0, 0.3, -0.2, 0.1, 2.6]
+    U = fields.random_smooth_state(mesh, 5, seed=seed + 1, base=st, amp=0.05)
+    gD = fields.face_values(mesh, fields.random_smooth_state(mesh, 5, seed=seed + 2, base=st, amp=0.05))
+    gN = 0.05 * fields.face_values(mesh, fields.random_smooth_state(mesh, 5, seed=seed + 3, base=None, amp=1.0))
+    return configs.Problem(f"box_mixed_ns_p{p}", mesh, configs.EQ_NS, 5, U, mu=0.05, gD=gD, gN=gN)
+
+
 def case(name):
+    if name == "poisson2d_mixed":
+        return poisson_mixed(3, 3, 2)
+    if name == "poisson3d_mixed":
+        return poisson_mixed(2, 2, 3)
+    if name == "channel_euler":
+        return channel_case(configs.EQ_EULER)
+    if name == "channel_ns":
+        return channel_case(configs.EQ_NS)
+    if name == "box_mixed_ns":
+        return box_mixed_ns()
     if name.endswith("_flip"):
         # the same workload on a mesh whose elements have reversed axes (S = -1 faces)
         pr = case(name[:-len("_flip")])

@@ -37,7 +37,8 @@ from tests.gpu_cases import case, gpu_of, oracle_of, record
 pytestmark = pytest.mark.gpu
 
 SMALL = ["C1", "ns2d_p1", "ns2d_p2", "ns2d_p3", "euler3d_p2", "poisson3d_p2", "tgv2p2", "tgv2p3", "tgv2p4",
-         "ns2d_p3_flip", "tgv2p3_flip", "tgv2p4_flip"]
+         "ns2d_p3_flip", "tgv2p3_flip", "tgv2p4_flip", "poisson2d_mixed", "poisson3d_mixed", "channel_euler",
+         "channel_ns", "box_mixed_ns"]
 PREC = {"f64": 0, "f32": 1, "bf16": 2}
 UNIT = {"f32": 2.0 ** -24, "bf16": 2.0 ** -8 + 2.0 ** -24}
 
@@ -126,11 +127,11 @@ def slots_to_dense_factors(orc, F_slots):
 
 
 @pytest.mark.parametrize("name", ["C1", "ns2d_p2", "ns2d_p3", "euler3d_p2", "tgv2p2", "tgv2p4", "ns2d_p3_flip",
-                                  "tgv2p3_flip"])
+                                  "tgv2p3_flip", "poisson2d_mixed", "channel_ns", "box_mixed_ns"])
 def test_precond_factors_and_apply_fp64(name):
     print(f"[gpu] bilu0 {name}", flush=True)
     pr = case(name)
-    alpha, gamma = (0.0, 1.0) if name == "C1" else (1.0, 0.02)
+    alpha, gamma = (0.0, 1.0) if (name == "C1" or name.startswith("poisson")) else (1.0, 0.02)
     ctx, U, K11, K12, F = assemble(pr, alpha, gamma)
     orc = oracle_of(pr)
     O11, O12, O21 = orc.jacobian(pr.U0)
@@ -189,7 +190,8 @@ def test_precond_low_precision_factors_apply_and_product(name, prec):
 
 
 @pytest.mark.parametrize("name", ["C1", "ns2d_p3", "euler3d_p2", "tgv2p3", "poisson3d_p2", "tgv2p4",
-                                  "ns2d_p3_flip", "tgv2p3_flip", "tgv2p4_flip"])
+                                  "ns2d_p3_flip", "tgv2p3_flip", "tgv2p4_flip", "poisson2d_mixed", "channel_euler",
+                                  "box_mixed_ns"])
 def test_jacvec_fp64_and_exact(name):
     print(f"[gpu] jacvec {name}", flush=True)
     pr = case(name)
@@ -238,7 +240,8 @@ def per_component_check(name, what, dg, do, tol):
 
 @pytest.mark.parametrize("name,prec", [("ns2d_p3", "f64"), ("ns2d_p3", "f32"), ("ns2d_p3", "bf16"),
                                        ("tgv2p3", "f64"), ("tgv2p3", "bf16"), ("tgv2p4", "f64"),
-                                       ("tgv2p4", "bf16"), ("ns2d_p3_flip", "bf16"), ("tgv2p3_flip", "f64")])
+                                       ("tgv2p4", "bf16"), ("ns2d_p3_flip", "bf16"), ("tgv2p3_flip", "f64"),
+                                       ("channel_ns", "bf16"), ("box_mixed_ns", "f64")])
 def test_bdf2_newton_step(name, prec):
     print(f"[gpu] newton {name} {prec}", flush=True)
     pr = case(name)
@@ -371,4 +374,31 @@ def test_bdf2_steps_keep_history_in_the_library():
         Uprev, Un = Un, Y
     per_component_check("ns2d_p2", "BDF2 x2 U2-U0", U.cpu().numpy() - pr.U0, Un.numpy() - pr.U0, 1e-7)
     assert torch.allclose(Up.cpu(), Uprev, rtol=0, atol=1e-8 * float(Uprev.abs().max()))
+    ctx.close()
+
+
+def test_backward_euler_pseudo_time_reaches_the_steady_state():
+    """Backward Euler with a growing step (Section 4.1: a sequence of increasing time steps for a
+    steady state) on the mixed Dirichlet / Neumann Poisson problem, whose exact solution u is in Q_p
+    and satisfies the discrete equations: the pseudo-time iterates reach the oracle's direct
+    steady solve and u itself."""
+    from paper_1204_1533_amd.ldg import LDG_BACKWARD_EULER
+    pr = case("poisson2d_mixed")
+    ctx = gpu_of(pr)
+    U = torch.zeros(pr.U0.shape, dtype=torch.float64, device="cuda")
+    dt = 1e-3
+    for k in range(12):
+        # ||G|| = ||U - U^n - dt R(U)|| has a rounding floor that grows with dt: absolute tolerance
+        r = ctx.ldg_implicit_step(U, None, dt, scheme=LDG_BACKWARD_EULER, max_newton=3, newton_rtol=1e-10,
+                                  newton_atol=1e-8, reuse=0, rtol=1e-11, restart=50, max_iters=3000)
+        assert r["converged"] == 1
+        dt *= 4.0
+    torch.cuda.synchronize()
+    orc = oracle_of(pr)
+    Ud = solver.steady_direct_solve(orc).numpy()
+    err = np.abs(U.cpu().numpy() - Ud).max()
+    record("poisson2d_mixed", "pseudo-time vs direct steady solve", err, 1e-8 * np.abs(Ud).max())
+    assert err <= 1e-8 * np.abs(Ud).max()
+    ue = pr.extra["u_exact"]
+    assert np.abs(U.cpu().numpy() - ue).max() <= 1e-8 * np.abs(ue).max()
     ctx.close()

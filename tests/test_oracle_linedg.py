@@ -6,7 +6,8 @@ import numpy as np
 import pytest
 import torch
 
-from ldg_workloads import configs, fields, hex_mesh, quad_mesh, reorient_elements
+from ldg_workloads import (BC_NEUMANN, BC_SLIP, configs, fields, hex_mesh, quad_mesh, reorient_elements,
+                           with_boundary_kinds)
 from oracle import LineDG, Physics
 from oracle.basis import LineOps
 from oracle.physics import EQ_EULER, EQ_NS, EQ_POISSON
@@ -321,3 +322,93 @@ def test_k21_weights_apply_as_homogeneous_gradient(kind):
     # the Jacobian's own K21 output is the same operator
     _, _, K21 = d.jacobian(fields.random_smooth_state(mesh, d.m, seed=5, base=base_state(mesh.dim), amp=0.05))
     assert torch.allclose(K21, W, rtol=0, atol=1e-13 * float(W.abs().max()))
+
+
+
+# ------------------------------------------------------------------ Neumann faces and slip walls (Section 3)
+@pytest.mark.parametrize("dim,p", [(2, 2), (2, 3), (3, 2)])
+def test_poisson_qp_exactness_mixed_dirichlet_neumann(dim, p):
+    """u in Q_p on a mesh of rectangular elements: g_D = u on the faces xi_n = 0 of the box and the
+    Neumann data g_N = F(u, grad u) . nhat = -grad u . nhat on the faces xi_n = 1 (eqs. neumann1/2
+    with C22 = 0): the discrete gradient is grad u and R = 0 at every node."""
+    if dim == 2:
+        base = quad_mesh(3, 3, p, box=((0.2, 1.4), (-0.3, 0.9)))
+        u, f, g = fields.poisson_polynomial(base, degs=(p, p - 1))
+    else:
+        base = hex_mesh(2, p, length=1.0, periodic=False, amp=0.0)
+        u, f, g = fields.poisson_polynomial_3d(base, degs=(p, 1, p))
+    mesh = with_boundary_kinds(base, {2 * n + 1: BC_NEUMANN for n in range(dim)})
+    gN = -fields.axis_normal_face_values(mesh, g)
+    d = disc(mesh, EQ_POISSON, source=f, gD=fields.face_values(mesh, u), gN=gN)
+    Q = d.gradient(u).numpy()
+    assert np.abs(Q - g).max() <= 1e-11 * np.abs(g).max()
+    R, mag = d.residual(u, return_abs=True)
+    assert R.abs().max() <= 1e-11 * mag.max()
+    # the Neumann data enters: other data changes R on the Neumann faces only
+    d2 = disc(mesh, EQ_POISSON, source=f, gD=fields.face_values(mesh, u), gN=gN + 1.0)
+    R2 = d2.residual(u)
+    assert R2.abs().max() > 1e-3
+
+
+def channel(p=3, eq=EQ_EULER, perturb=0.2):
+    """Periodic in x, slip walls at y = 0 and y = 2 (straight: boundary vertices are not moved)."""
+    base = quad_mesh(4, 3, p, box=((0, 4), (0, 2)), periodic=(True, False), perturb=perturb, seed=3)
+    return with_boundary_kinds(base, {0 + 2: BC_SLIP, 1 + 2: BC_SLIP})
+
+
+@pytest.mark.parametrize("eq", [EQ_EULER, EQ_NS])
+def test_slip_wall_uniform_flow_along_the_wall(eq):
+    """Flow parallel to a slip wall is its own mirror state, so the wall flux is the physical
+    pressure flux and a uniform flow stays steady (R = 0) on the perturbed channel mesh."""
+    mesh = channel(eq=eq)
+    U = fields.constant_state(mesh, [1.0, 0.5, 0.0, 2.6])
+    d = disc(mesh, eq, mu=0.05)
+    R = d.residual(U)
+    assert float(R.abs().max()) <= 1e-12 * flux_scale(d, [1.0, 0.5, 0.0, 2.6])
+
+
+@pytest.mark.parametrize("eq", [EQ_EULER, EQ_NS])
+def test_slip_wall_conserves_mass_and_energy(eq):
+    """Through a slip wall the Roe flux of the mirror state carries no mass and no energy (its
+    central part and its dissipation both vanish there), so on the channel mass and energy are
+    conserved discretely while the wall-normal momentum is not (the wall pressure force)."""
+    mesh = channel(eq=eq)
+    d = disc(mesh, eq, mu=0.05)
+    U = fields.random_smooth_state(mesh, d.m, seed=9, base=base_state(2), amp=0.1)
+    R, mag = d.residual(U, return_abs=True)
+    geo = d.geometry(torch.arange(d.E))
+    w = weights3(d)
+    tot = (R * geo["J"][:, None, :] * w).sum(dim=(0, 2))
+    scale = (mag * geo["J"][:, None, :].abs() * w).sum(dim=(0, 2))
+    assert abs(float(tot[0])) <= 1e-13 * float(scale[0])
+    assert abs(float(tot[3])) <= 1e-13 * float(scale[3])
+    assert abs(float(tot[2])) > 1e-6 * float(scale[2])
+
+
+@pytest.mark.parametrize("eq,kind", [(EQ_EULER, BC_SLIP), (EQ_NS, BC_SLIP), (EQ_POISSON, BC_NEUMANN),
+                                     (EQ_NS, BC_NEUMANN)])
+def test_jacobian_vs_finite_differences_with_boundaries(eq, kind):
+    """Jacobians (dual numbers) against central differences of the residual on a mesh with
+    Dirichlet faces and Neumann faces or slip walls (P8 with boundaries)."""
+    p = 2
+    base = quad_mesh(2, 2, p, box=((0, 2), (0, 2)), periodic=(True, False), perturb=0.2, seed=1)
+    mesh = with_boundary_kinds(base, {3: kind})
+    m = 1 if eq == EQ_POISSON else 4
+    state = [0.4] if eq == EQ_POISSON else base_state(2)
+    gD = fields.face_values(mesh, fields.random_smooth_state(mesh, m, seed=5, base=state, amp=0.05))
+    gN = 0.1 * fields.face_values(mesh, fields.random_smooth_state(mesh, m, seed=6, base=None, amp=1.0))
+    d = disc(mesh, eq, mu=0.1, gD=gD, gN=gN, c11_interior=0.3 if eq == EQ_POISSON else 0.0)
+    U = fields.random_smooth_state(mesh, m, seed=3, base=state, amp=0.05)
+    K11, K12, K21 = d.jacobian(U)
+    A = solver.dense_operator(d, K11, K12, K21)
+    rng = np.random.default_rng(0)
+    for _ in range(2):
+        v = rng.standard_normal(U.shape)
+        eps = 1e-6
+        fd = ((d.residual(U + eps * v) - d.residual(U - eps * v)) / (2 * eps)).numpy().reshape(-1)
+        assert np.abs(fd - A @ v.reshape(-1)).max() <= 1e-6 * np.abs(fd).max()
+    # K21 weights reproduce the homogeneous gradient (inside traces on Neumann faces and walls)
+    x = torch.as_tensor(rng.standard_normal(U.shape))
+    w = apply_k21(d, d.k21(), x)
+    ref = d.gradient(x, homogeneous=True)
+    assert float((w - ref).abs().max()) <= 1e-12 * float(ref.abs().max())
