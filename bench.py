@@ -72,7 +72,7 @@ def roofline(pr, reps, prec):
     Algorithmic bytes per node (m components, D dimensions, p degree, e bytes per stored entry):
       split product: K11 (Dp+1+2D) m^2 e + K12 (Dp+1+D) m^2 D e + x 8m + w = K21 x 8mD + y 8m
       ILU(0) apply : factors (Dp+1) m^2 e + r 8m + z 8m
-      K21 x        : x 8m + node coordinates 8D + w 8mD
+      K21 x        : stored weights (Dp+1+D) D 8 + x 8m + w 8mD
     """
     import numpy as np
     me = pr.mesh
@@ -82,10 +82,10 @@ def roofline(pr, reps, prec):
     per_node = {
         "jacvec": (D * p + 1 + 2 * D) * m * m * e + (D * p + 1 + D) * m * m * D * e + 8 * m + 8 * m * D + 8 * m,
         "precond_apply": (D * p + 1) * m * m * e + 16 * m,
-        "k21_gradient": 8 * m + 8 * D + 8 * m * D,
+        "k21_product": (D * p + 1 + D) * D * 8 + 8 * m + 8 * m * D,
     }
     keys = {"jacvec": ("t_jacvec_ms", "n_jacvec"), "precond_apply": ("t_precond_ms", "n_precond"),
-            "k21_gradient": ("t_k21_ms", "n_k21")}
+            "k21_product": ("t_k21_ms", "n_k21")}
     allk = {}
     for k, (tk, nk) in keys.items():
         tot = float(np.sum([r[tk] for r in reps]))

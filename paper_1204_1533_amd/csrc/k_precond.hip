@@ -1,8 +1,9 @@
 // Split Jacobian-vector product and the element-local line-pattern
 // preconditioner (Section 4.2 of the paper).
 //
-// jacvec:   y = alpha x - gamma (K11 x + K12 w), w = K21 x computed by the
-//           gradient kernel with zero boundary data (eq. matvecsplit).  One
+// jacvec:   y = alpha x - gamma (K11 x + K12 w), w = K21 x from the stored
+//           K21 weights (eq. matvecsplit; K21 is the gradient operator with
+//           zero boundary data, a function of the geometry only).  One
 //           thread per node streams its block row (node-fastest layout, so a
 //           wavefront reads contiguous memory for every (slot, c, c')); the
 //           workgroup holds whole elements and stages their x and w in LDS.

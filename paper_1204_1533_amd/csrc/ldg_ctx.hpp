@@ -25,6 +25,7 @@ struct ldg_ctx_s {
   double* d_Q = nullptr;   // Q scratch (residual)
   double* d_W = nullptr;   // K21 x scratch
   double* d_W2 = nullptr;  // tangent Q scratch
+  double* d_K21w = nullptr;  // stored K21 weights [slot][d][E Np], computed on first use
   // assembled state
   bool assembled = false;
   int prec = 0;

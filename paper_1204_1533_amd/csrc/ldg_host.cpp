@@ -75,7 +75,8 @@ void ldg_destroy(ldg_ctx c) {
   if (!c) return;
   void* ptrs[] = {c->d_xyz, c->d_face_nbr, c->d_nbr_node, c->d_sw, c->d_gD, c->d_gN, c->d_S, c->d_Q, c->d_W, c->d_W2,
                   c->d_K11, c->d_K12, c->d_F, c->d_Fem, c->d_Ua, c->d_Qa, c->d_V, c->d_Z, c->d_R, c->d_G, c->d_x, c->d_r, c->d_z,
-                  c->d_tmp, c->d_Un, c->d_partial, c->d_h, c->d_Uold, c->d_st_Un, c->d_st_comb, c->d_st_K};
+                  c->d_tmp, c->d_Un, c->d_partial, c->d_h, c->d_Uold, c->d_st_Un, c->d_st_comb, c->d_st_K,
+                  c->d_K21w};
   for (void* p : ptrs)
     if (p) hipFree(p);
   learned_free(c);
@@ -281,6 +282,12 @@ static ldg_status assemble(ldg_ctx c, const double* U, double alpha, double gamm
   const int ns11 = dc.D * dc.P + 1 + 2 * dc.D, ns12 = dc.D * dc.P + 1 + dc.D, nsF = dc.D * dc.P + 1;
   TRY(grow(c, &c->d_K11, &c->capK11, es * (size_t)ns11 * dc.M * dc.M * c->nnode));
   TRY(grow(c, &c->d_K12, &c->capK12, es * (size_t)ns12 * dc.M * dc.M * dc.D * c->nnode));
+  if (dc.EQ != LDG_EULER && !c->d_K21w) {
+    // K21 = dD/dU depends on the geometry only: its weights are computed at the
+    // first assembly and serve every product after it
+    TRY(dev_alloc(c, &c->d_K21w, (size_t)(dc.D * dc.P + 1 + dc.D) * dc.D * c->nnode));
+    HIPCK(c, launch_k21_weights(dc, c->d_K21w));
+  }
   const int fprec = prec;
   const size_t nF = (size_t)nsF * dc.M * dc.M * c->nnode;
   // A~ is formed node-fastest in d_F (FP64 for FP64 storage, FP32 otherwise),
@@ -323,7 +330,10 @@ ldg_status apply_op_with(ldg_ctx c, const double* x, double* y, bool exact, doub
   const bool vis = dc.EQ != LDG_EULER;
   if (vis) {
     Span sp(c, 1);
-    HIPCK(c, launch_gradient(dc, x, W, true));
+    if (c->d_K21w)
+      HIPCK(c, launch_k21_apply(dc, c->d_K21w, x, W));
+    else
+      HIPCK(c, launch_gradient(dc, x, W, true));
   }
   if (exact) {
     // y = alpha x - gamma dR/dU x  (tangent of the FP64 residual at the assembled state)

@@ -53,6 +53,11 @@ hipError_t launch_residual(const DevCtx& c, const double* U, const double* Q, do
 hipError_t launch_residual_tangent(const DevCtx& c, const double* U, const double* V, const double* Q,
                                    const double* Qt, double* Rt);
 
+// K21 = dD/dU as stored FP64 weights [slot][d][E Np] (D p + 1 + D slots),
+// computed once from the geometry; w = K21 x with them.
+hipError_t launch_k21_weights(const DevCtx& c, double* Wt);
+hipError_t launch_k21_apply(const DevCtx& c, const double* Wt, const double* x, double* w);
+
 // Jacobian blocks; prec: 0 f64, 1 f32, 2 bf16.  Layout [slot][row comp][col comp][E*Np].
 hipError_t launch_jacobian(const DevCtx& c, const double* U, const double* Q, void* K11, void* K12, int prec);
 
