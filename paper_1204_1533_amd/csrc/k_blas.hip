@@ -61,14 +61,14 @@ __global__ void multidot_finish_kernel(const double* __restrict__ partial, int n
 
 __global__ void __launch_bounds__(NT_BLAS) update_kernel(double* __restrict__ w, const double* __restrict__ V,
                                                         int64_t ldv, int k, const double* __restrict__ h,
-                                                        int64_t n, double sign) {
+                                                        int64_t n, double sign, double scale) {
   __shared__ double sh[128];
   for (int j = threadIdx.x; j < k; j += NT_BLAS) sh[j] = h[j];
   __syncthreads();
   for (int64_t i = (int64_t)blockIdx.x * NT_BLAS + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT_BLAS) {
     double acc = 0.0;
     for (int j = 0; j < k; ++j) acc += V[(int64_t)j * ldv + i] * sh[j];
-    w[i] += sign * acc;
+    w[i] = (w[i] + sign * acc) * scale;
   }
 }
 
@@ -110,16 +110,17 @@ hipError_t launch_multidot_finish(const double* partial, int nblocks, int k, dou
   return hipGetLastError();
 }
 
-hipError_t launch_update(double* w, const double* V, int64_t ldv, int k, const double* h, int64_t n, hipStream_t s) {
+hipError_t launch_update(double* w, const double* V, int64_t ldv, int k, const double* h, int64_t n, hipStream_t s,
+                         double scale) {
   if (k > 128) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(update_kernel, dim3(grid_for(n, NT_BLAS)), dim3(NT_BLAS), 0, s, w, V, ldv, k, h, n, -1.0);
+  hipLaunchKernelGGL(update_kernel, dim3(grid_for(n, NT_BLAS)), dim3(NT_BLAS), 0, s, w, V, ldv, k, h, n, -1.0, scale);
   return hipGetLastError();
 }
 
 hipError_t launch_lincomb(double* y, const double* V, int64_t ldv, int k, const double* coef, int64_t n,
                           hipStream_t s) {
   if (k > 128) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(update_kernel, dim3(grid_for(n, NT_BLAS)), dim3(NT_BLAS), 0, s, y, V, ldv, k, coef, n, 1.0);
+  hipLaunchKernelGGL(update_kernel, dim3(grid_for(n, NT_BLAS)), dim3(NT_BLAS), 0, s, y, V, ldv, k, coef, n, 1.0, 1.0);
   return hipGetLastError();
 }
 

@@ -515,11 +515,6 @@ template <int NJP> struct RowRegs<PREC_BF16, NJP> {
 #pragma unroll
     for (int ch = 0; ch < NJP / 4; ++ch) v[ch] = p[(base + (int64_t)ch * NR * 4) / 4];
   }
-  // hides the values from the compiler so that their conversion is not hoisted out of the level loops
-  __device__ __forceinline__ void opaque() {
-#pragma unroll
-    for (int ch = 0; ch < NJP / 4; ++ch) asm volatile("" : "+v"(v[ch].x), "+v"(v[ch].y));
-  }
   __device__ __forceinline__ double get(int j) const {
     const uint32_t w = (j & 2) ? v[j >> 2].y : v[j >> 2].x;
     return bf16_to_f32((uint16_t)((j & 1) ? (w >> 16) : (w & 0xFFFFu)));
@@ -531,10 +526,6 @@ template <int NJP> struct RowRegs<PREC_F32, NJP> {
     const float4* p = reinterpret_cast<const float4*>(F);
 #pragma unroll
     for (int ch = 0; ch < NJP / 4; ++ch) v[ch] = p[(base + (int64_t)ch * NR * 4) / 4];
-  }
-  __device__ __forceinline__ void opaque() {
-#pragma unroll
-    for (int ch = 0; ch < NJP / 4; ++ch) asm volatile("" : "+v"(v[ch].x), "+v"(v[ch].y), "+v"(v[ch].z), "+v"(v[ch].w));
   }
   __device__ __forceinline__ double get(int j) const {
     const float4& q = v[j >> 2];
@@ -552,7 +543,6 @@ template <int NJP> struct RowRegs<PREC_F64, NJP> {
       v[2 * ch + 1] = p[(base + (int64_t)ch * NR * 4) / 2 + 1];
     }
   }
-  __device__ __forceinline__ void opaque() {}
   __device__ __forceinline__ double get(int j) const { return (j & 1) ? v[j >> 1].y : v[j >> 1].x; }
 };
 
@@ -598,10 +588,27 @@ struct ApplyShape {
 // a_{D-1} are independent.  The work items of an element take the rows of one
 // level at a time (one row each: node a, component c); the factor rows are
 // stored in level order, so a level's rows are one contiguous run read with
-// 8- to 32-byte loads, and the next level's rows are fetched while the current
-// one is computed.  y_a = r_a - sum_{k < a} L_ak y_k, then
+// 8- to 32-byte loads.  y_a = r_a - sum_{k < a} L_ak y_k, then
 // z_a = U_aa^{-1} (y_a - sum_{j > a} U_aj z_j) with the inverse diagonal block
-// stored in the diagonal slot; y and z live in LDS in natural order.
+// stored in the diagonal slot.  y and t live in LDS node-major (the m values
+// of a node in one 16-byte aligned run, read with 16-byte loads).  A row is
+// loaded when its level starts, not one level ahead: the loads of the other
+// resident workgroups hide the latency, and registers for a second row would
+// halve the workgroups per CU.
+template <int M>
+struct NodeRun {
+  static constexpr int YS = (M + 1) / 2 * 2;  // doubles per node in LDS
+  double v[YS];
+  __device__ __forceinline__ void load(const double* base) {
+#pragma unroll
+    for (int q = 0; q < YS; q += 2) {
+      const double2 w = *reinterpret_cast<const double2*>(base + q);
+      v[q] = w.x;
+      v[q + 1] = w.y;
+    }
+  }
+};
+
 template <int D, int P, int EQ, int FP>
 __global__ void __launch_bounds__((ApplyShape<D, P, EQ>::NT)) apply_kernel(LevelOrder ord, int64_t E,
                                                                           const void* __restrict__ F,
@@ -610,95 +617,84 @@ __global__ void __launch_bounds__((ApplyShape<D, P, EQ>::NT)) apply_kernel(Level
   using S = FacShape<D, P, EQ>;
   using A = ApplyShape<D, P, EQ>;
   constexpr int N1 = P + 1, NP = S::NP, M = S::M, NSL = S::NSL, NR = S::NR, NJP = S::NJP;
-  constexpr int TPE = A::TPE, EPB = A::EPB, NL = D * P;
-  __shared__ double sy[EPB * NR];
-  __shared__ double st[EPB * NR];
+  constexpr int TPE = A::TPE, EPB = A::EPB, NL = D * P, YS = NodeRun<M>::YS;
+  __shared__ __align__(16) double sy[EPB * NP * YS];
+  __shared__ __align__(16) double st[EPB * NP * YS];
   const int tid = threadIdx.x;
   const int le = tid / TPE, lane = tid % TPE;
   const int64_t e = (int64_t)blockIdx.x * EPB + le;
   const bool live = le < EPB && e < E;
-  double* y = sy + (le < EPB ? le : 0) * NR;
-  double* t = st + (le < EPB ? le : 0) * NR;
+  double* y = sy + (le < EPB ? le : 0) * NP * YS;
+  double* t = st + (le < EPB ? le : 0) * NP * YS;
   if (live)
-    for (int i = lane; i < NR; i += TPE) y[i] = r[e * NR + i];
+    for (int i = lane; i < NR; i += TPE) y[(i % NP) * YS + i / NP] = r[e * NR + i];
   __syncthreads();
+  RowRegs<FP, NJP> f;
   // forward sweep over levels 1..NL (level 0 has no lower entries)
-  RowRegs<FP, NJP> f, fn;
-  {
-    const int row = ord.off[1] * M + lane;
-    if (live && row < ord.off[2] * M) f.load(F, fac_index(e, row, 0, NR, NJP), NR);
-  }
   for (int L = 1; L <= NL; ++L) {
     const int row = ord.off[L] * M + lane;
-    const bool act = live && row < ord.off[L + 1] * M;
-    if (L < NL) {
-      const int rn = ord.off[L + 1] * M + lane;
-      if (live && rn < ord.off[L + 2] * M) fn.load(F, fac_index(e, rn, 0, NR, NJP), NR);
-    }
-    if (act) {
+    if (live && row < ord.off[L + 1] * M) {
+      f.load(F, fac_index(e, row, 0, NR, NJP), NR);
       const int a = ord.node[row / M], c = row % M;
-      double acc = y[c * NP + a];
+      double acc = y[a * YS + c];
 #pragma unroll
       for (int s = 0; s < NSL; ++s) {
         const int k = slot_col<D, P>(a, s);
         if (k < a) {
+          NodeRun<M> yk;
+          yk.load(y + k * YS);
           double tt = 0.0;  // one block row at a time: short dependency chains
 #pragma unroll
-          for (int q = 0; q < M; ++q) tt += f.get(s * M + q) * y[q * NP + k];
+          for (int q = 0; q < M; ++q) tt += f.get(s * M + q) * yk.v[q];
           acc -= tt;
         }
       }
-      y[c * NP + a] = acc;
+      y[a * YS + c] = acc;
     }
     __syncthreads();
-    f = fn;
   }
   // backward sweep over levels NL..0
-  {
-    const int row = ord.off[NL] * M + lane;
-    if (live && row < ord.off[NL + 1] * M) f.load(F, fac_index(e, row, 0, NR, NJP), NR);
-  }
   for (int L = NL; L >= 0; --L) {
     const int row = ord.off[L] * M + lane;
     const bool act = live && row < ord.off[L + 1] * M;
-    if (L > 0) {
-      const int rn = ord.off[L - 1] * M + lane;
-      if (live && rn < ord.off[L] * M) fn.load(F, fac_index(e, rn, 0, NR, NJP), NR);
-    }
     int a = 0, c = 0;
     if (act) {
+      f.load(F, fac_index(e, row, 0, NR, NJP), NR);
       a = ord.node[row / M];
       c = row % M;
-      double acc = y[c * NP + a];
+      double acc = y[a * YS + c];
 #pragma unroll
       for (int s = 0; s < NSL; ++s) {
         const int j = slot_col<D, P>(a, s);
         if (j > a) {
+          NodeRun<M> zj;
+          zj.load(y + j * YS);
           double tt = 0.0;
 #pragma unroll
-          for (int q = 0; q < M; ++q) tt += f.get(s * M + q) * y[q * NP + j];
+          for (int q = 0; q < M; ++q) tt += f.get(s * M + q) * zj.v[q];
           acc -= tt;
         }
       }
-      t[c * NP + a] = acc;
+      t[a * YS + c] = acc;
     }
     __syncthreads();
     if (act) {
       const int self = a % N1;
+      NodeRun<M> ta;
+      ta.load(t + a * YS);
       double v = 0.0;
 #pragma unroll
       for (int s = 0; s < N1; ++s)
         if (s == self) {
 #pragma unroll
-          for (int q = 0; q < M; ++q) v += f.get(s * M + q) * t[q * NP + a];
+          for (int q = 0; q < M; ++q) v += f.get(s * M + q) * ta.v[q];
         }
-      y[c * NP + a] = v;
+      y[a * YS + c] = v;
     }
     __syncthreads();
-    f = fn;
   }
   if (live)
-    for (int i = lane; i < NR; i += TPE) z[e * NR + i] = y[i];
+    for (int i = lane; i < NR; i += TPE) z[e * NR + i] = y[(i % NP) * YS + i / NP];
 }
 
 // element-major factors [E Np][slot][c][c'] -> apply layout (zero padding)

@@ -399,7 +399,7 @@ static ldg_status norm2(ldg_ctx c, const double* w, double* out) {
 }
 
 // Right-preconditioned GMRES(restart) on (alpha I - gamma A) x = b, x0 = 0,
-// classical Gram-Schmidt with one re-orthogonalisation.  The operator is the
+// classical Gram-Schmidt with a selective second pass.  The operator is the
 // stored split product (exact = false) or the exact tangent (exact = true).
 // true_res: end with the true residual ||b - A x|| in *est_res (else the
 // Arnoldi estimate; the refinement loop computes the exact residual itself).
@@ -440,19 +440,37 @@ static ldg_status gmres(ldg_ctx c, const double* b, double* x, double rtol_abs, 
         TRY(precond_apply_any(c, vk, zk));
       }
       TRY(apply_op(c, zk, w, exact));
-      // CGS2
-      TRY(dots(c, c->d_V, k + 1, w, h.data()));
-      HIPCK(c, hipMemcpyAsync(c->d_h, h.data(), sizeof(double) * (k + 1), hipMemcpyHostToDevice, dc.stream));
-      HIPCK(c, launch_update(w, c->d_V, n, k + 1, c->d_h, n, dc.stream));
-      TRY(dots(c, c->d_V, k + 1, w, h2.data()));
-      HIPCK(c, hipMemcpyAsync(c->d_h, h2.data(), sizeof(double) * (k + 1), hipMemcpyHostToDevice, dc.stream));
-      HIPCK(c, launch_update(w, c->d_V, n, k + 1, c->d_h, n, dc.stream));
+      // Classical Gram-Schmidt, repeated once when the projection removed more
+      // than half of |w|^2 (the Daniel-Gragg-Kaufman-Stewart criterion with
+      // eta = 1/sqrt 2).  w = V_{k+1} follows V_k in memory, so one pass gives
+      // V_j . w (j <= k) and w . w; with V orthonormal, |w - V h|^2 = w.w - |h|^2,
+      // and the normalisation is folded into the update.
+      double hn = 0.0;
+      bool done = false;
+      std::fill(h2.begin(), h2.end(), 0.0);
+      for (int pass = 0; pass < 2 && !done; ++pass) {
+        double* hp = pass == 0 ? h.data() : h2.data();
+        TRY(dots(c, c->d_V, k + 2, w, hp));
+        double hh = 0.0;
+        for (int j = 0; j <= k; ++j) hh += hp[j] * hp[j];
+        const double ww = hp[k + 1], rest = ww - hh;
+        HIPCK(c, hipMemcpyAsync(c->d_h, hp, sizeof(double) * (k + 1), hipMemcpyHostToDevice, dc.stream));
+        if (rest > 0.5 * ww) {
+          hn = std::sqrt(rest);
+          HIPCK(c, launch_update(w, c->d_V, n, k + 1, c->d_h, n, dc.stream, 1.0 / hn));
+          done = true;
+        } else {
+          HIPCK(c, launch_update(w, c->d_V, n, k + 1, c->d_h, n, dc.stream));
+        }
+      }
+      if (!done) {
+        // near breakdown (or non-finite values): the norm is taken explicitly
+        TRY(norm2(c, w, &hn));
+        if (hn > 0 && std::isfinite(hn)) HIPCK(c, launch_axpby(w, 0.0, w, 1.0 / hn, n, dc.stream));
+      }
       for (int j = 0; j <= k; ++j) H[j * restart + k] = h[j] + h2[j];
-      double hn;
-      TRY(norm2(c, w, &hn));
       H[(k + 1) * restart + k] = hn;
       if (!std::isfinite(hn)) return fail(c, LDG_E_NONFINITE, "non-finite Arnoldi vector");
-      if (hn > 0) HIPCK(c, launch_axpby(w, 0.0, w, 1.0 / hn, n, dc.stream));
       for (int j = 0; j < k; ++j) {
         double t = cs[j] * H[j * restart + k] + sn[j] * H[(j + 1) * restart + k];
         H[(j + 1) * restart + k] = -sn[j] * H[j * restart + k] + cs[j] * H[(j + 1) * restart + k];

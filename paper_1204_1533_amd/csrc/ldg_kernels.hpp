@@ -81,7 +81,7 @@ hipError_t launch_multidot(const double* V, int64_t ldv, int k, const double* w,
                            int nblocks, hipStream_t s);
 hipError_t launch_multidot_finish(const double* partial, int nblocks, int k, double* out, hipStream_t s);
 hipError_t launch_update(double* w, const double* V, int64_t ldv, int k, const double* h, int64_t n,
-                         hipStream_t s);  // w -= V h (h on device)
+                         hipStream_t s, double scale = 1.0);  // w = (w - V h) scale (h on device)
 hipError_t launch_axpby(double* y, double a, const double* x, double b, int64_t n, hipStream_t s);  // y = a x + b y
 hipError_t launch_lincomb(double* y, const double* V, int64_t ldv, int k, const double* coef, int64_t n,
                           hipStream_t s);  // y += V coef
