@@ -13,7 +13,7 @@
  *  - Every call returns an ldg_status; no C++ exception crosses the ABI.  On
  *    failure ldg_last_error(ctx) returns a message (thread-unsafe, per ctx);
  *    ldg_last_error(NULL) returns the message of this thread's last failed
- *    ldg_create.
+ *    call that takes no context (ldg_create, ldg_assign_switches).
  *  - Arrays named *_dev are device pointers owned by the caller (e.g. torch
  *    tensors on cuda:0), contiguous, float64, in the documented layout.  They
  *    must not alias unless a call says so.  Arrays named *_host are host
@@ -97,6 +97,21 @@ typedef struct {
  * reported later as LDG_E_NONFINITE), LDG_E_UNSUPPORTED (dim/p/equation or
  * boundary kind outside the built set). */
 ldg_status ldg_create(const ldg_problem_desc* desc, void* hip_stream, ldg_ctx* out);
+
+/* Section 3 (switch function, figure switchplt): a switch function for a mesh
+ * with arbitrarily oriented elements, written to switch_plus_host [E][D]
+ * (host memory, caller-owned), ready for ldg_problem_desc.switch_plus_host.
+ * Host computation only (no device work, no context).  A chord enters an
+ * element through a face of local direction n and leaves it through the other
+ * face of direction n; one sign per chord makes the two elements of every
+ * shared face carry opposite signs.  Chords are started in element order, then
+ * local-direction order, with S^+ = +1 on the starting element, so the result
+ * is unique (all +1 on a mesh whose elements are all aligned).
+ * face_nbr_host [E][2D] and nbr_node_host [E][2D][Nf] as in ldg_problem_desc.
+ * Errors: LDG_E_INVALID (dim, p, E, null pointers), LDG_E_SHAPE (a neighbour
+ * out of range, or no face of the neighbour maps back to the face). */
+ldg_status ldg_assign_switches(int32_t dim, int32_t p, int64_t n_elem, const int64_t* face_nbr_host,
+                               const int32_t* nbr_node_host, int8_t* switch_plus_host);
 void ldg_destroy(ldg_ctx ctx);
 
 /* Source term S (eq. conslaw), added to R; S_dev [E][m][Np], copied.  NULL clears. */

@@ -215,15 +215,18 @@ def hex_mesh(n: int, p: int, length: float = 2 * math.pi, periodic: bool = True,
     return Mesh(3, p, np.ascontiguousarray(xyz), face_nbr, nbr_node, sw, name=name)
 
 
-def reorient_elements(mesh: Mesh, flips: np.ndarray, perm: np.ndarray | None = None) -> Mesh:
-    """Relabel a mesh: reverse local axes of some elements and renumber elements.
+def reorient_elements(mesh: Mesh, flips: np.ndarray, perm: np.ndarray | None = None,
+                      axes: np.ndarray | None = None) -> Mesh:
+    """Relabel a mesh: rotate the local frames of some elements and renumber elements.
 
-    ``flips[e, n]`` reverses local axis ``n`` of element ``e`` (so its faces
-    ``2n`` and ``2n+1`` swap).  Each element must flip an even number of axes so
-    that the mapping keeps a positive Jacobian determinant.  ``perm`` renumbers elements (new index
-    ``perm[old]``).  Coordinates, connectivity, the coinciding-node map and the
-    switch signs are all updated consistently, so the discrete operator is only
-    relabelled.  Returns the new mesh.
+    New local axis ``n`` of element ``e`` is old axis ``axes[e, n]`` (identity
+    when ``axes`` is None), reversed when ``flips[e, n]``; so new face ``2n + s``
+    is old face ``2 axes[e, n] + s`` (or ``+ 1 - s`` when flipped).  The map must
+    keep a positive Jacobian determinant: the permutation's sign times
+    (-1)^(number of flips) is +1 (in 3-D these are the 24 rotations of the cube).
+    ``perm`` renumbers elements (new index ``perm[old]``).  Coordinates,
+    connectivity, the coinciding-node map and the switch signs are all updated
+    consistently, so the discrete operator is only relabelled.  Returns the new mesh.
     """
     dim, p = mesh.dim, mesh.p
     n1 = p + 1
@@ -232,8 +235,16 @@ def reorient_elements(mesh: Mesh, flips: np.ndarray, perm: np.ndarray | None = N
     nf = n1 ** (dim - 1)
     if perm is None:
         perm = np.arange(E)
-    if np.any(np.sum(flips, axis=1) % 2):
-        raise ValueError("an odd number of flipped axes would make det(G) negative")
+    if axes is None:
+        axes = np.tile(np.arange(dim), (E, 1))
+    axes = np.asarray(axes)
+    for e in range(E):
+        if sorted(axes[e].tolist()) != list(range(dim)):
+            raise ValueError("axes[e] must be a permutation")
+        # sign of the permutation by counting inversions
+        inv = sum(1 for i in range(dim) for j in range(i + 1, dim) if axes[e, i] > axes[e, j])
+        if (inv + int(np.sum(flips[e]))) % 2:
+            raise ValueError("the relabelling would make det(G) negative")
     # node relabelling per element: new local node -> old local node
     idx = np.stack(np.meshgrid(*([np.arange(n1)] * dim), indexing="ij"), axis=0)
     idx = idx[::-1].reshape(dim, -1)  # idx[d, node] = coordinate d of node (i fastest)
@@ -245,10 +256,9 @@ def reorient_elements(mesh: Mesh, flips: np.ndarray, perm: np.ndarray | None = N
     new_to_old = np.empty((E, Np), dtype=np.int64)
     old_to_new = np.empty((E, Np), dtype=np.int64)
     for e in range(E):
-        c = idx.copy()
+        c = np.empty_like(idx)
         for d in range(dim):
-            if flips[e, d]:
-                c[d] = p - c[d]
+            c[axes[e, d]] = p - idx[d] if flips[e, d] else idx[d]
         old = node_of(c)  # new node k corresponds to old node old[k]
         new_to_old[e] = old
         old_to_new[e, old] = np.arange(Np)
@@ -260,26 +270,49 @@ def reorient_elements(mesh: Mesh, flips: np.ndarray, perm: np.ndarray | None = N
         ne = perm[e]
         xyz[ne] = mesh.xyz[e][:, new_to_old[e]]
         for n in range(dim):
-            sw[ne, n] = -mesh.switch_plus[e, n] if flips[e, n] else mesh.switch_plus[e, n]
+            no = int(axes[e, n])
+            sw[ne, n] = -mesh.switch_plus[e, no] if flips[e, n] else mesh.switch_plus[e, no]
             for s in (0, 1):
-                so = (1 - s) if flips[e, n] else s          # old face index for new face s
-                fo, fn = 2 * n + so, 2 * n + s
+                so = (1 - s) if flips[e, n] else s          # old side for new side s
+                fo, fn = 2 * no + so, 2 * n + s
                 nb = mesh.face_nbr[e, fo]
                 face_nbr[ne, fn] = perm[nb] if nb >= 0 else nb
                 for l in range(nf):
                     # new face node l -> new node -> old node -> old face line index
                     new_node = line_end_node(dim, p, n, l, p if s == 1 else 0)
                     old_node = new_to_old[e, new_node]
-                    # find old face line index lo of old_node on old face fo
                     lo = None
                     for cand in range(nf):
-                        if line_end_node(dim, p, n, cand, p if so == 1 else 0) == old_node:
+                        if line_end_node(dim, p, no, cand, p if so == 1 else 0) == old_node:
                             lo = cand
                             break
                     if nb >= 0:
                         old_nb_node = mesh.nbr_node[e, fo, lo]
                         nbr_node[ne, fn, l] = old_to_new[nb, old_nb_node]
     return Mesh(dim, p, xyz, face_nbr, nbr_node, sw, name=mesh.name + "+relabelled")
+
+
+def random_rotations(dim: int, E: int, seed: int, frac: float = 1.0):
+    """Seeded orientation-preserving local frames for ``reorient_elements``: for a
+    fraction ``frac`` of the elements a uniformly drawn rotation of the square / cube
+    (axis permutation with flips of matching parity), the identity for the rest.
+    Returns (axes, flips)."""
+    import itertools
+    rng = np.random.default_rng(seed)
+    rots = []
+    for pa in itertools.permutations(range(dim)):
+        inv = sum(1 for i in range(dim) for j in range(i + 1, dim) if pa[i] > pa[j])
+        for fl in itertools.product((False, True), repeat=dim):
+            if (inv + sum(fl)) % 2 == 0:
+                rots.append((pa, fl))
+    axes = np.tile(np.arange(dim), (E, 1))
+    flips = np.zeros((E, dim), dtype=bool)
+    for e in range(E):
+        if rng.random() < frac:
+            pa, fl = rots[rng.integers(len(rots))]
+            axes[e] = pa
+            flips[e] = fl
+    return axes, flips
 
 
 # boundary kinds of a face: face_nbr = -(kind + 1)

@@ -191,6 +191,7 @@ ldg_status apply_op_with(ldg_ctx c, const double* x, double* y, bool exact, doub
 ldg_status learned_after_form(ldg_ctx c, const double* R_at_U, double gamma);
 ldg_status precond_apply_any(ldg_ctx c, const double* r, double* z);
 void learned_free(ldg_ctx c);
+void set_host_error(const std::string& m);  // message for ldg_last_error(NULL)
 ldg_status net_forward(ldg_net net, const float* X, const uint16_t* Xb, int64_t n, int prec, float* Y);
 
 }  // namespace ldg_host

@@ -64,8 +64,14 @@ const char* ldg_status_string(ldg_status s) {
   return "unknown status";
 }
 
-// Message of the last failed ldg_create on this thread (no context exists then).
+// Message of the last failed call without a context on this thread
+// (ldg_create, ldg_assign_switches).
 static thread_local std::string g_create_err;
+}  // extern "C"
+namespace ldg_host {
+void set_host_error(const std::string& m) { g_create_err = m; }
+}  // namespace ldg_host
+extern "C" {
 
 const char* ldg_last_error(ldg_ctx ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
 

@@ -89,6 +89,7 @@ _P = ctypes.c_void_p
 _SIGS = {
     "ldg_create": (ctypes.c_int, [ctypes.POINTER(ldg_problem_desc), _P, ctypes.POINTER(_P)]),
     "ldg_destroy": (None, [_P]),
+    "ldg_assign_switches": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _P, _P, _P]),
     "ldg_set_source": (ctypes.c_int, [_P, _P]),
     "ldg_set_dirichlet": (ctypes.c_int, [_P, _P]),
     "ldg_set_neumann": (ctypes.c_int, [_P, _P]),
@@ -159,6 +160,19 @@ def _ptr(t):
     if isinstance(t, int):
         return t
     return t.data_ptr()
+
+
+def ldg_assign_switches(dim, p, face_nbr, nbr_node):
+    """Switch function S^+ [E][D] (int8) for the given connectivity (host arrays)."""
+    lib = load_library()
+    fn = np.ascontiguousarray(face_nbr, dtype=np.int64)
+    nn = np.ascontiguousarray(nbr_node, dtype=np.int32)
+    out = np.zeros((fn.shape[0], dim), dtype=np.int8)
+    st = lib.ldg_assign_switches(int(dim), int(p), int(fn.shape[0]), fn.ctypes.data, nn.ctypes.data,
+                                 out.ctypes.data)
+    if st != LDG_OK:
+        raise LDGError(st, lib.ldg_last_error(None).decode())
+    return out
 
 
 class Context:

@@ -65,17 +65,37 @@ def flip_mesh(mesh, seed, frac=0.5):
     return reorient_elements(mesh, flips, perm), flips, perm
 
 
-def relabel_nodal(V, mesh, flips, perm):
-    """A nodal field [E][C][Np] of the original mesh in the numbering of the flipped mesh."""
+def rotate_mesh(mesh, seed, frac=1.0):
+    """Rotate the local frames of a seeded random subset of elements by any rotation of the
+    square / cube (axis permutations with flips), renumber the elements, and give the result
+    the switch function of the chord algorithm.  Returns (mesh, flips, perm, axes)."""
+    from ldg_workloads import random_rotations, reorient_elements
+    from ldg_workloads.mesh import Mesh
+    from oracle.switches import assign_switches
+    rng = np.random.default_rng(seed)
+    axes, flips = random_rotations(mesh.dim, mesh.n_elem, seed + 1, frac)
+    perm = rng.permutation(mesh.n_elem)
+    m2 = reorient_elements(mesh, flips, perm, axes)
+    sw = assign_switches(m2.dim, m2.p, m2.face_nbr, m2.nbr_node)
+    m3 = Mesh(m2.dim, m2.p, m2.xyz, m2.face_nbr, m2.nbr_node, sw, name=m2.name + "+chords")
+    return m3, flips, perm, axes
+
+
+def relabel_nodal(V, mesh, flips, perm, axes=None):
+    """A nodal field [E][C][Np] of the original mesh in the numbering of the relabelled mesh
+    (new local axis d = old axis axes[e, d], reversed where flips[e, d])."""
     n1, D = mesh.p + 1, mesh.dim
     idx = np.arange(mesh.np_)
     coords = [(idx // n1 ** d) % n1 for d in range(D)]
     out = np.empty_like(V)
     for e in range(mesh.n_elem):
+        ax = range(D) if axes is None else axes[e]
+        c_old = [None] * D
+        for d, a in enumerate(ax):
+            c_old[a] = mesh.p - coords[d] if flips[e, d] else coords[d]
         old = np.zeros_like(idx)
-        for d in reversed(range(D)):
-            c = mesh.p - coords[d] if flips[e, d] else coords[d]
-            old = old * n1 + c
+        for a in reversed(range(D)):
+            old = old * n1 + c_old[a]
         out[perm[e]] = V[e][:, old]
     return out
 
@@ -139,6 +159,16 @@ def case(name):
         mesh2, flips, perm = flip_mesh(pr.mesh, seed=17)
         U2 = relabel_nodal(pr.U0, pr.mesh, flips, perm)
         return configs.Problem(pr.name + "_flip", mesh2, pr.equation, pr.m, U2, gamma=pr.gamma, mu=pr.mu,
+                               prandtl=pr.prandtl, c11_interior=pr.c11_interior,
+                               c11_dirichlet=pr.c11_dirichlet, dt=pr.dt, extra=dict(pr.extra))
+    if name.endswith("_rot"):
+        # the same workload on a mesh whose element frames are rotated (axis permutations and
+        # reversals), renumbered, with the switch function of the chord algorithm
+        pr = case(name[:-len("_rot")])
+        assert pr.source is None and pr.gD is None
+        mesh2, flips, perm, axes = rotate_mesh(pr.mesh, seed=23)
+        U2 = relabel_nodal(pr.U0, pr.mesh, flips, perm, axes)
+        return configs.Problem(pr.name + "_rot", mesh2, pr.equation, pr.m, U2, gamma=pr.gamma, mu=pr.mu,
                                prandtl=pr.prandtl, c11_interior=pr.c11_interior,
                                c11_dirichlet=pr.c11_dirichlet, dt=pr.dt, extra=dict(pr.extra))
     if name == "C1":

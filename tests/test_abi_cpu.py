@@ -133,3 +133,38 @@ def test_time_step_and_newton_validate_before_device_work(lib):
     assert lib.ldg_implicit_step(None, None, None, 0.1, ctypes.byref(so), ctypes.byref(lo),
                                  ctypes.byref(rep)) == ldg.LDG_E_INVALID
     assert lib.ldg_newton_step(None, None, None, 1.0, 0.1, ctypes.byref(lo), None) == ldg.LDG_E_INVALID
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_assign_switches_matches_oracle(lib, dim):
+    """The library's chord switch function (host code, no device) equals the oracle's
+    element for element on meshes with rotated and renumbered elements."""
+    from ldg_workloads import hex_mesh, random_rotations, reorient_elements
+    from oracle.switches import assign_switches
+    from paper_1204_1533_amd.ldg import ldg_assign_switches
+    if dim == 2:
+        base = quad_mesh(5, 4, 3, box=((0, 5), (0, 4)), periodic=(True, False), perturb=0.1, seed=3)
+    else:
+        base = hex_mesh(3, 2, length=3.0, periodic=True, amp=0.05)
+    axes, flips = random_rotations(dim, base.n_elem, 21, frac=0.7)
+    perm = np.random.default_rng(22).permutation(base.n_elem)
+    m = reorient_elements(base, flips, perm, axes)
+    S_lib = ldg_assign_switches(dim, m.p, m.face_nbr, m.nbr_node)
+    S_orc = assign_switches(dim, m.p, m.face_nbr, m.nbr_node)
+    assert np.array_equal(S_lib, S_orc)
+    assert np.any(S_lib < 0)
+    # aligned mesh: all +1
+    assert np.all(ldg_assign_switches(dim, base.p, base.face_nbr, base.nbr_node) == 1)
+
+
+def test_assign_switches_rejects_broken_connectivity(lib):
+    from paper_1204_1533_amd.ldg import LDGError, ldg_assign_switches
+    m = quad_mesh(3, 3, 2, box=((0, 3), (0, 3)), periodic=(True, True))
+    nn = m.nbr_node.copy()
+    nn[4, 1, :] = nn[4, 1, ::-1]  # face 1 of element 4 no longer maps back
+    with pytest.raises(LDGError) as ei:
+        ldg_assign_switches(2, m.p, m.face_nbr, nn)
+    assert ei.value.status == -2 and "not reciprocal" in str(ei.value)
+    with pytest.raises(LDGError) as ei:
+        ldg_assign_switches(4, m.p, m.face_nbr, m.nbr_node)
+    assert ei.value.status == -1

@@ -37,8 +37,8 @@ from tests.gpu_cases import case, gpu_of, oracle_of, record
 pytestmark = pytest.mark.gpu
 
 SMALL = ["C1", "ns2d_p1", "ns2d_p2", "ns2d_p3", "euler3d_p2", "poisson3d_p2", "tgv2p2", "tgv2p3", "tgv2p4",
-         "ns2d_p3_flip", "tgv2p3_flip", "tgv2p4_flip", "poisson2d_mixed", "poisson3d_mixed", "channel_euler",
-         "channel_ns", "box_mixed_ns"]
+         "ns2d_p3_flip", "tgv2p3_flip", "tgv2p4_flip", "ns2d_p3_rot", "tgv2p3_rot", "poisson2d_mixed",
+         "poisson3d_mixed", "channel_euler", "channel_ns", "box_mixed_ns"]
 PREC = {"f64": 0, "f32": 1, "bf16": 2}
 UNIT = {"f32": 2.0 ** -24, "bf16": 2.0 ** -8 + 2.0 ** -24}
 
@@ -87,7 +87,7 @@ def test_jacobian_blocks_fp64(name):
 
 
 @pytest.mark.parametrize("name,prec", [("ns2d_p3", "f32"), ("ns2d_p3", "bf16"), ("tgv2p4", "f32"),
-                                       ("tgv2p4", "bf16"), ("tgv2p3_flip", "bf16")])
+                                       ("tgv2p4", "bf16"), ("tgv2p3_flip", "bf16"), ("tgv2p3_rot", "bf16")])
 def test_jacobian_stored_precision(name, prec):
     pr = case(name)
     print(f"[gpu] jacobian {name} {prec}", flush=True)
@@ -127,7 +127,8 @@ def slots_to_dense_factors(orc, F_slots):
 
 
 @pytest.mark.parametrize("name", ["C1", "ns2d_p2", "ns2d_p3", "euler3d_p2", "tgv2p2", "tgv2p4", "ns2d_p3_flip",
-                                  "tgv2p3_flip", "poisson2d_mixed", "channel_ns", "box_mixed_ns"])
+                                  "tgv2p3_flip", "ns2d_p3_rot", "tgv2p3_rot", "poisson2d_mixed", "channel_ns",
+                                  "box_mixed_ns"])
 def test_precond_factors_and_apply_fp64(name):
     print(f"[gpu] bilu0 {name}", flush=True)
     pr = case(name)
@@ -190,8 +191,8 @@ def test_precond_low_precision_factors_apply_and_product(name, prec):
 
 
 @pytest.mark.parametrize("name", ["C1", "ns2d_p3", "euler3d_p2", "tgv2p3", "poisson3d_p2", "tgv2p4",
-                                  "ns2d_p3_flip", "tgv2p3_flip", "tgv2p4_flip", "poisson2d_mixed", "channel_euler",
-                                  "box_mixed_ns"])
+                                  "ns2d_p3_flip", "tgv2p3_flip", "tgv2p4_flip", "ns2d_p3_rot", "tgv2p3_rot",
+                                  "poisson2d_mixed", "channel_euler", "box_mixed_ns"])
 def test_jacvec_fp64_and_exact(name):
     print(f"[gpu] jacvec {name}", flush=True)
     pr = case(name)
@@ -241,7 +242,8 @@ def per_component_check(name, what, dg, do, tol):
 @pytest.mark.parametrize("name,prec", [("ns2d_p3", "f64"), ("ns2d_p3", "f32"), ("ns2d_p3", "bf16"),
                                        ("tgv2p3", "f64"), ("tgv2p3", "bf16"), ("tgv2p4", "f64"),
                                        ("tgv2p4", "bf16"), ("ns2d_p3_flip", "bf16"), ("tgv2p3_flip", "f64"),
-                                       ("channel_ns", "bf16"), ("box_mixed_ns", "f64")])
+                                       ("channel_ns", "bf16"), ("box_mixed_ns", "f64"), ("ns2d_p3_rot", "f64"),
+                                       ("tgv2p3_rot", "bf16")])
 def test_bdf2_newton_step(name, prec):
     print(f"[gpu] newton {name} {prec}", flush=True)
     pr = case(name)

@@ -41,8 +41,8 @@ pytestmark = pytest.mark.gpu
 
 FULL = ["C1", "C2", "ns2d_p1", "ns2d_p2", "ns2d_p3", "ns2d_p4", "euler3d_p1", "euler3d_p2", "euler3d_p3",
         "euler3d_p4", "poisson3d_p2", "poisson3d_p3", "tgv3p2", "tgv2p4", "ns2d_p3_flip", "ns2d_p4_flip",
-        "euler3d_p3_flip", "tgv2p3_flip", "tgv2p4_flip", "poisson2d_mixed", "poisson3d_mixed", "channel_euler",
-        "channel_ns", "box_mixed_ns"]
+        "euler3d_p3_flip", "tgv2p3_flip", "tgv2p4_flip", "ns2d_p3_rot", "euler3d_p3_rot", "tgv2p3_rot",
+        "poisson2d_mixed", "poisson3d_mixed", "channel_euler", "channel_ns", "box_mixed_ns"]
 
 
 def run_gpu(pr, want_q=True):
