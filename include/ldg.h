@@ -57,6 +57,7 @@ typedef enum {
 
 typedef enum { LDG_POISSON = 0, LDG_EULER = 1, LDG_NS = 2 } ldg_equation;
 typedef enum { LDG_F64 = 0, LDG_F32 = 1, LDG_BF16 = 2 } ldg_precision;
+typedef enum { LDG_PRECOND_BILU0 = 0, LDG_PRECOND_BLOCK_LU = 1 } ldg_precond_kind;
 
 /* Problem description (host memory, copied by ldg_create).
  * Section 2.1: the element nodes are the images x(X_ijk) of a tensor grid of
@@ -173,9 +174,20 @@ ldg_status ldg_jacvec_noalloc(ldg_ctx ctx, const double* x_dev, double* y_dev, i
  * element, forward and backward block substitution in natural node order; the
  * paper factorises each block by a sparse direct LU and names ILU as an
  * improvement), plus the learned correction when the current assembly applies
- * one.  Linear in r.  r_dev, z_dev [E][m][Np], may not alias.
+ * one; or, when the assembly was made with LDG_PRECOND_BLOCK_LU, the exact LU
+ * of each element block.  Linear in r.  r_dev, z_dev [E][m][Np], may not alias.
  * Error: LDG_E_NOT_ASSEMBLED. */
 ldg_status ldg_precond_apply(ldg_ctx ctx, const double* r_dev, double* z_dev);
+
+/* Section 4.2: how the element blocks of A~ are factorised from the next
+ * ldg_jacobian_assemble on (also inside ldg_newton_step / ldg_implicit_step).
+ * LDG_PRECOND_BILU0 (default): block ILU(0), storage precision as assembled.
+ * LDG_PRECOND_BLOCK_LU: the paper's exact factorisation of each block -- A~_e
+ * (formed as for BILU(0)) expanded to a dense NR x NR matrix, NR = Np m,
+ * factorised in FP64 without pivoting, E NR^2 doubles of device memory; no
+ * learned correction with it.  Changing the kind invalidates the assembly.
+ * Errors: LDG_E_INVALID (kind), LDG_E_UNSUPPORTED (block LU with Np m > 768). */
+ldg_status ldg_set_preconditioner(ldg_ctx ctx, int32_t kind);
 
 /* Copy the assembled operators out in FP64, line-block layout:
  * K11_dev [E][Np][Dp+1+2D][m][m], K12_dev [E][Np][Dp+1+D][m][m*D] (columns

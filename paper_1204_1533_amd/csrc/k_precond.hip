@@ -775,9 +775,10 @@ static unsigned copy_grid(int64_t n) {
 // transposed to the element-major layout in the second half of Fwork and
 // factorised there in place (FP64 arithmetic for FP64 factors, FP32
 // otherwise), then rearranged into the apply layout in Fem in storage
-// precision fprec.
+// precision fprec.  With dense != null the element-major A~ is instead
+// expanded and factorised exactly (dense [E][NR][NR] LU in FP64).
 hipError_t launch_precond_factor(const DevCtx& dc, const void* K11, const void* K12, int prec, double alpha,
-                                 double gamma, void* Fwork, int fprec, void* Fem, float* At_copy) {
+                                 double gamma, void* Fwork, int fprec, void* Fem, float* At_copy, double* dense) {
   const int64_t NN = dc.E * dc.NP;
   const int nsl = dc.D * dc.P + 1;
   const int nq = nsl * dc.M * dc.M;
@@ -799,6 +800,7 @@ hipError_t launch_precond_factor(const DevCtx& dc, const void* K11, const void* 
           hipLaunchKernelGGL((convert_kernel<PREC_F64, PREC_F32>), dim3(copy_grid(nF)), dim3(256), 0, dc.stream, Fwork,
                              At_copy, nF);
         hipLaunchKernelGGL((relayout_kernel<PREC_F64>), tgrid, dim3(256), 0, dc.stream, Fwork, em, NN, nq);
+        if (dense) return launch_blocklu_factor(dc, em, PREC_F64, dense);
         hipLaunchKernelGGL((factor_kernel<D, P, EQ, PREC_F64>), dim3((unsigned)dc.E), dim3(64), 0, dc.stream, dc.E,
                            em);
         hipLaunchKernelGGL((em_to_fac_kernel<PREC_F64, PREC_F64>), dim3(copy_grid(nFac)), dim3(256), 0, dc.stream, dc.lev,
@@ -813,6 +815,7 @@ hipError_t launch_precond_factor(const DevCtx& dc, const void* K11, const void* 
           hipLaunchKernelGGL((convert_kernel<PREC_F32, PREC_F32>), dim3(copy_grid(nF)), dim3(256), 0, dc.stream, Fwork,
                              At_copy, nF);
         hipLaunchKernelGGL((relayout_kernel<PREC_F32>), tgrid, dim3(256), 0, dc.stream, Fwork, em, NN, nq);
+        if (dense) return launch_blocklu_factor(dc, em, PREC_F32, dense);
         hipLaunchKernelGGL((factor_kernel<D, P, EQ, PREC_F32>), dim3((unsigned)dc.E), dim3(64), 0, dc.stream, dc.E, em);
         if (fprec == PREC_BF16)
           hipLaunchKernelGGL((em_to_fac_kernel<PREC_F32, PREC_BF16>), dim3(copy_grid(nFac)), dim3(256), 0, dc.stream,

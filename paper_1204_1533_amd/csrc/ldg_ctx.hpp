@@ -25,9 +25,13 @@ struct ldg_ctx_s {
   double* d_Q = nullptr;   // Q scratch (residual)
   double* d_W = nullptr;   // K21 x scratch
   double* d_W2 = nullptr;  // tangent Q scratch
+  int precond_kind = 0;       // ldg_precond_kind: 0 BILU(0), 1 exact element-block LU
+  double* d_Dense = nullptr;  // [E][NR][NR] dense L\U of A~ (block LU)
+  size_t capDense = 0;
   double* d_K21w = nullptr;  // stored K21 weights [slot][d][E Np], computed on first use
   // assembled state
   bool assembled = false;
+  int assembled_kind = 0;  // preconditioner built by the last assembly
   int prec = 0;
   double alpha = 1.0, gamma = 0.0;
   void* d_K11 = nullptr;

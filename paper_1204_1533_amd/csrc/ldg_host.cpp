@@ -82,7 +82,7 @@ void ldg_destroy(ldg_ctx c) {
   void* ptrs[] = {c->d_xyz, c->d_face_nbr, c->d_nbr_node, c->d_sw, c->d_gD, c->d_gN, c->d_S, c->d_Q, c->d_W, c->d_W2,
                   c->d_K11, c->d_K12, c->d_F, c->d_Fem, c->d_Ua, c->d_Qa, c->d_V, c->d_Z, c->d_R, c->d_G, c->d_x, c->d_r, c->d_z,
                   c->d_tmp, c->d_Un, c->d_partial, c->d_h, c->d_Uold, c->d_st_Un, c->d_st_comb, c->d_st_K,
-                  c->d_K21w};
+                  c->d_K21w, c->d_Dense};
   for (void* p : ptrs)
     if (p) hipFree(p);
   learned_free(c);
@@ -309,12 +309,18 @@ static ldg_status assemble(ldg_ctx c, const double* U, double alpha, double gamm
   const bool vis = dc.EQ != LDG_EULER;
   if (vis) HIPCK(c, launch_gradient(dc, U, c->d_Qa, false));
   HIPCK(c, launch_jacobian(dc, U, vis ? c->d_Qa : nullptr, c->d_K11, c->d_K12, prec));
-  const bool keep = c->learned_collect || (c->net && c->learned_enabled);
+  const bool block_lu = c->precond_kind == LDG_PRECOND_BLOCK_LU;
+  const bool keep = !block_lu && (c->learned_collect || (c->net && c->learned_enabled));
   if (keep) TRY(dev_alloc(c, &c->d_At, nF));
   c->learned_kept = keep;
   c->learned_active = false;
+  if (block_lu) {
+    const size_t NR = (size_t)dc.NP * dc.M;
+    TRY(grow(c, (void**)&c->d_Dense, &c->capDense, sizeof(double) * dc.E * NR * NR));
+  }
   HIPCK(c, launch_precond_factor(dc, c->d_K11, c->d_K12, prec, alpha, gamma, c->d_F, fprec, c->d_Fem,
-                                 keep ? c->d_At : nullptr));
+                                 keep ? c->d_At : nullptr, block_lu ? c->d_Dense : nullptr));
+  c->assembled_kind = c->precond_kind;
   c->assembled = true;
   c->prec = prec;
   c->alpha = alpha;
@@ -325,6 +331,16 @@ static ldg_status assemble(ldg_ctx c, const double* U, double alpha, double gamm
 
 ldg_status ldg_jacobian_assemble(ldg_ctx c, const double* U, double alpha, double gamma, int32_t prec) {
   return assemble(c, U, alpha, gamma, prec, nullptr);
+}
+
+ldg_status ldg_set_preconditioner(ldg_ctx c, int32_t kind) {
+  if (!c) return LDG_E_INVALID;
+  if (kind != LDG_PRECOND_BILU0 && kind != LDG_PRECOND_BLOCK_LU) return fail(c, LDG_E_INVALID, "preconditioner kind");
+  if (kind == LDG_PRECOND_BLOCK_LU && c->dc.NP * c->dc.M > 768)
+    return fail(c, LDG_E_UNSUPPORTED, "block LU needs Np m <= 768");
+  if (kind != c->precond_kind) c->assembled = false;  // the factors must be rebuilt
+  c->precond_kind = kind;
+  return LDG_OK;
 }
 
 }  // extern "C"
@@ -383,6 +399,8 @@ ldg_status ldg_export_operators(ldg_ctx c, double* K11, double* K12, double* F) 
   const int ns11 = dc.D * dc.P + 1 + 2 * dc.D, ns12 = dc.D * dc.P + 1 + dc.D;
   if (K11) HIPCK(c, launch_export_blocks(dc, c->d_K11, c->prec, ns11, dc.M, K11));
   if (K12) HIPCK(c, launch_export_blocks(dc, c->d_K12, c->prec, ns12, dc.M * dc.D, K12));
+  if (F && c->assembled_kind == LDG_PRECOND_BLOCK_LU)
+    return fail(c, LDG_E_UNSUPPORTED, "F: the preconditioner is the dense element-block LU");
   if (F) HIPCK(c, launch_factors_to_f64(dc, c->d_Fem, c->prec, F));
   return LDG_OK;
 }

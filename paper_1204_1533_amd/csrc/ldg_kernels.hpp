@@ -69,7 +69,12 @@ hipError_t launch_jacvec(const DevCtx& c, const void* K11, const void* K12, int 
 // K21 weights (node-fastest in Fwork), then factorised by block ILU(0): the
 // factors end in Fem in the apply layout above (precision fprec).
 hipError_t launch_precond_factor(const DevCtx& c, const void* K11, const void* K12, int prec, double alpha,
-                                 double gamma, void* Fwork, int fprec, void* Fem, float* At_copy);
+                                 double gamma, void* Fwork, int fprec, void* Fem, float* At_copy,
+                                 double* dense = nullptr);
+// exact element-block LU of A~: element-major A~ (FP64 or FP32) -> dense
+// [E][NR][NR] L\U (FP64, unit lower L), NR = Np m <= 768; and its apply
+hipError_t launch_blocklu_factor(const DevCtx& c, const void* em, int emprec, double* dense);
+hipError_t launch_blocklu_apply(const DevCtx& c, const double* dense, const double* r, double* z);
 hipError_t launch_factors_to_f64(const DevCtx& c, const void* Fem, int fprec, double* out);
 hipError_t launch_precond_apply(const DevCtx& c, const void* Fem, int fprec, const double* r, double* z);
 

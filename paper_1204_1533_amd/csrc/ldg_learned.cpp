@@ -188,6 +188,10 @@ ldg_status learned_after_form(ldg_ctx c, const double* R_at_U, double gamma) {
 
 ldg_status precond_apply_any(ldg_ctx c, const double* r, double* z) {
   const DevCtx& dc = c->dc;
+  if (c->assembled_kind == LDG_PRECOND_BLOCK_LU) {
+    HIPCK(c, launch_blocklu_apply(dc, c->d_Dense, r, z));
+    return LDG_OK;
+  }
   if (!c->learned_active) {
     HIPCK(c, launch_precond_apply(dc, c->d_Fem, c->prec, r, z));
     return LDG_OK;

@@ -15,6 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libldg.so")
 
 LDG_OK = 0
+LDG_PRECOND_BILU0, LDG_PRECOND_BLOCK_LU = 0, 1
 LDG_E_INVALID, LDG_E_SHAPE, LDG_E_UNSUPPORTED, LDG_E_HIP = -1, -2, -3, -4
 LDG_E_NOMEM, LDG_E_NOT_ASSEMBLED, LDG_E_NOT_CONVERGED, LDG_E_NONFINITE = -5, -6, -7, -8
 LDG_POISSON, LDG_EULER, LDG_NS = 0, 1, 2
@@ -89,6 +90,7 @@ _P = ctypes.c_void_p
 _SIGS = {
     "ldg_create": (ctypes.c_int, [ctypes.POINTER(ldg_problem_desc), _P, ctypes.POINTER(_P)]),
     "ldg_destroy": (None, [_P]),
+    "ldg_set_preconditioner": (ctypes.c_int, [_P, ctypes.c_int32]),
     "ldg_assign_switches": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _P, _P, _P]),
     "ldg_set_source": (ctypes.c_int, [_P, _P]),
     "ldg_set_dirichlet": (ctypes.c_int, [_P, _P]),
@@ -249,6 +251,9 @@ class Context:
 
     def ldg_jacvec_noalloc(self, x, y, exact_fp64=False):
         self._check(self.lib.ldg_jacvec_noalloc(self.h, _ptr(x), _ptr(y), int(exact_fp64)))
+
+    def ldg_set_preconditioner(self, kind):
+        self._check(self.lib.ldg_set_preconditioner(self.h, int(kind)))
 
     def ldg_precond_apply(self, r, z):
         self._check(self.lib.ldg_precond_apply(self.h, _ptr(r), _ptr(z)))
