@@ -370,6 +370,7 @@ __global__ void __launch_bounds__(NT_ELEM) jac_kernel(LineOps ops_arg, MeshParam
 hipError_t launch_jacobian(const DevCtx& dc, const double* U, const double* Q, void* K11, void* K12, int prec) {
   LDG_DISPATCH(dc, {
     using L = JacLayout<D, P, EQ>;
+    static_assert(L::bytes <= LDS_PER_CU, "assembly workspace must fit one CU's LDS");
     LDG_PREC_DISPATCH(prec, {
       auto k11 = jac_kernel<D, P, EQ, PR, 0, 1>;
       auto k12 = jac_kernel<D, P, EQ, PR, 1, 1 + D>;

@@ -240,6 +240,7 @@ __global__ void __launch_bounds__(256) k21_apply_kernel(MeshParams mp, const dou
 hipError_t launch_k21_weights(const DevCtx& dc, double* Wt) {
   LDG_DISPATCH(dc, {
     using L = K21Layout<D, P>;
+    static_assert(L::bytes <= LDS_PER_CU, "weights workspace must fit one CU's LDS");
     auto k = k21_weights_kernel<D, P>;
     if (L::bytes > 65536) {
       hipError_t err = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L::bytes);

@@ -788,12 +788,17 @@ hipError_t launch_precond_factor(const DevCtx& dc, const void* K11, const void* 
   const dim3 tgrid((unsigned)((NN + 63) / 64), (unsigned)((nq + 31) / 32));
   LDG_DISPATCH(dc, {
     using L = FormLayout<D, P, EQ>;
+    static_assert(L::bytes <= LDS_PER_CU, "formation workspace must fit one CU's LDS");
     const size_t bytes = Eq<D, EQ>::VIS ? L::bytes : 0;
     LDG_PREC_DISPATCH(prec, {
       if (fprec == PREC_F64) {
         double* em = (double*)Fwork + nF;
         auto k = form_kernel<D, P, EQ, PR, PREC_F64>;
-        if (bytes > 65536) hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (bytes > 65536) {
+          const hipError_t err =
+              hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+          if (err != hipSuccess) return err;
+        }
         hipLaunchKernelGGL(k, dim3((unsigned)dc.E), dim3(NT_ELEM), bytes, dc.stream, dc.ops, dc.mp, K11, K12, alpha,
                            gamma, Fwork);
         if (At_copy)
@@ -808,7 +813,11 @@ hipError_t launch_precond_factor(const DevCtx& dc, const void* K11, const void* 
       } else {
         float* em = (float*)Fwork + nF;
         auto k = form_kernel<D, P, EQ, PR, PREC_F32>;
-        if (bytes > 65536) hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (bytes > 65536) {
+          const hipError_t err =
+              hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+          if (err != hipSuccess) return err;
+        }
         hipLaunchKernelGGL(k, dim3((unsigned)dc.E), dim3(NT_ELEM), bytes, dc.stream, dc.ops, dc.mp, K11, K12, alpha,
                            gamma, Fwork);
         if (At_copy)

@@ -422,6 +422,7 @@ static hipError_t launch_elem(K kernel, size_t bytes, int64_t E, int epb, hipStr
 hipError_t launch_residual(const DevCtx& dc, const double* U, const double* Q, double* R) {
   LDG_DISPATCH(dc, {
     using L = ResidLayout<D, P, EQ, double>;
+    static_assert(L::bytes <= LDS_PER_CU, "residual workspace must fit one CU's LDS");
     return launch_elem(resid_kernel<D, P, EQ, double>, L::bytes, dc.E, L::EPB, dc.stream, dc.ops, dc.mp, U, nullptr,
                        Q, nullptr, R);
   })
@@ -431,6 +432,7 @@ hipError_t launch_residual_tangent(const DevCtx& dc, const double* U, const doub
                                    const double* Qt, double* Rt) {
   LDG_DISPATCH(dc, {
     using L = ResidLayout<D, P, EQ, Dual<1>>;
+    static_assert(L::bytes <= LDS_PER_CU, "tangent workspace must fit one CU's LDS");
     return launch_elem(resid_kernel<D, P, EQ, Dual<1>>, L::bytes, dc.E, L::EPB, dc.stream, dc.ops, dc.mp, U, V, Q,
                        Qt, Rt);
   })
@@ -439,6 +441,7 @@ hipError_t launch_residual_tangent(const DevCtx& dc, const double* U, const doub
 hipError_t launch_gradient(const DevCtx& dc, const double* U, double* Q, bool homogeneous) {
   LDG_DISPATCH(dc, {
     using L = GradLayout<D, P, EQ>;
+    static_assert(L::bytes <= LDS_PER_CU, "gradient workspace must fit one CU's LDS");
     auto kern = grad_kernel<D, P, EQ>;
     if (L::bytes > 65536) {
       hipError_t err = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L::bytes);

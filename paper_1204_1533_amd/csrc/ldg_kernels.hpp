@@ -19,6 +19,7 @@ struct DevCtx {
 
 // Block size of the element kernels.
 constexpr int NT_ELEM = 256;
+constexpr size_t LDS_PER_CU = 160 * 1024;  // bytes of LDS one workgroup may use on gfx950
 
 // Elements per workgroup for the residual-type kernels: small 2-D elements
 // are packed so that one workgroup still has several hundred work items.
