@@ -11,17 +11,22 @@
 //   d r_t / d u_nbr(xi=1) = L1_t dFhat^+/du_out,  d r_t / d u_nbr(xi=0) = L0_t dFhat^-/du_out,
 // and the same with q in place of u for K12; rows are scaled by -1/J.
 //
-// One workgroup per element.  For each part (u, then q_{:,d} for d < D) and
-// each direction, the m x m flux Jacobians at all Gauss points and line ends
-// are formed in LDS; then one thread per (row node, component pair) contracts
-// them into every slot of its block row.  The self slot sums the D directions
-// in LDS, so each output is written exactly once, and consecutive threads
-// write consecutive nodes of the [slot][c][c'][node] layout.
-// Flux Jacobians: d/du by m forward-mode passes with one tangent each (the
-// gradient held constant); d/dq exactly, since the viscous flux is linear in q
-// with no q-free part (column k of dF/dq_{:,d} is F^vis(u, e_{k,d})) and the
-// inviscid and penalty terms do not involve q.  The 1-D operators are copied
-// to LDS because every lane indexes them by its own line position.
+// Three launches:
+//   geometry (once per context)  Gauss-point metrics a_n, face normals and
+//            -1/J of every node, from the node coordinates;
+//   points   one work item per Gauss point of every line of every direction
+//            (and one per line end): the m x m flux Jacobians d f~ . a_n / du
+//            (m forward-mode passes with one tangent each, the gradient held
+//            constant) and d f~ . a_n / dq_{:,d} (exact: the viscous flux is
+//            linear in q with no q-free part, so column k is F^vis(u, e_{k,d})),
+//            written to a workspace with the point index fastest;
+//   contract one work item per (element, part, component pair, row node)
+//            contracts the point Jacobians of the node's D lines into every
+//            slot of its block row; the self slot sums the D directions in a
+//            register, so each output is written exactly once, and
+//            consecutive work items write consecutive nodes of the
+//            [slot][c][c'][node] layout.
+// No launch holds more than the 1-D operators in LDS.
 #include "ldg_dispatch.hpp"
 #include "ldg_kernels.hpp"
 #include "ldg_store.hpp"
@@ -29,73 +34,55 @@
 namespace ldg {
 
 template <int D, int P, int EQ>
-struct JacLayout {
+struct JacShape {
   static constexpr int N1 = P + 1, NG = n_gauss(P), NP = ipow(N1, D), NL = ipow(N1, D - 1);
   static constexpr int M = Eq<D, EQ>::M;
   static constexpr bool VIS = Eq<D, EQ>::VIS;
-  static constexpr int QW = VIS ? M * D : 0;
-  static constexpr int oU = 0;
-  static constexpr int oQ = oU + M * NP;
-  static constexpr int oX = oQ + QW * NP;
-  static constexpr int oG = oX + D * NP;
-  static constexpr int oJ = oG + D * D * NP;
-  static constexpr int oA = oJ + NP;
-  static constexpr int oFi = oA + NL * NG * M * M;
-  static constexpr int oFo = oFi + NL * 2 * M * M;
-  static constexpr int oOps = oFo + NL * 2 * M * M;  // copy of the 1-D operators
-  static constexpr int oDiag = oOps + (int)(sizeof(LineOps) / sizeof(double));
-  static constexpr int NITEM_ = (NP * M * M + NT_ELEM - 1) / NT_ELEM;
-  static constexpr int ndoubles = oDiag + NITEM_ * NT_ELEM;  // per-thread self-slot sums
-  static constexpr size_t bytes = sizeof(double) * ndoubles;
-  static constexpr int NITEM = (NP * M * M + NT_ELEM - 1) / NT_ELEM;
+  static constexpr int NPART = VIS ? 1 + D : 1;  // u, then q_{:,d}
+  static constexpr int MM = M * M;
+  static constexpr int NLG = NL * NG;            // Gauss points of one direction
+  static constexpr int NLS = NL * 2;             // line ends of one direction
+  // volume workspace [E][D][NPART][MM][NLG]; face workspace [E][D][NPART][2 sides][MM][NLS]
+  static constexpr int64_t VOL = (int64_t)D * NPART * MM * NLG;
+  static constexpr int64_t FACE = (int64_t)D * NPART * 2 * MM * NLS;
+  static constexpr int NITEM = (NP * MM + NT_ELEM - 1) / NT_ELEM;
   static constexpr int NS11 = D * P + 1 + 2 * D;
   static constexpr int NS12 = D * P + 1 + D;
 };
 
-template <int D, int N1>
-__device__ __forceinline__ int line_slot(int n, int t, int tp) {
-  // slot of column position tp on the row's direction-n line (row at position t), tp != t for n > 0
-  return n == 0 ? tp : N1 + (n - 1) * (N1 - 1) + (tp < t ? tp : tp - 1);
+// Geometry record of an element: [Ag: D][NLG][D] Gauss-point metric a_n,
+// [Nf: D][NLS][D] outward non-unit normals of the line ends, [Js: NP] -1/J.
+template <int D, int P>
+struct GeoShape {
+  static constexpr int N1 = P + 1, NG = n_gauss(P), NP = ipow(N1, D), NL = ipow(N1, D - 1);
+  static constexpr int oAg = 0;
+  static constexpr int oNf = oAg + D * NL * NG * D;
+  static constexpr int oJs = oNf + D * NL * 2 * D;
+  static constexpr int REC = oJs + NP;
+};
+
+// LDS copy of the 1-D operators (per-lane indexing of a kernel argument would
+// need private copies)
+__device__ __forceinline__ const LineOps& stage_ops(const LineOps& ops_arg, double* dst) {
+  const double* src = reinterpret_cast<const double*>(&ops_arg);
+  for (int i = threadIdx.x; i < (int)(sizeof(LineOps) / sizeof(double)); i += blockDim.x) dst[i] = src[i];
+  __syncthreads();
+  return *reinterpret_cast<const LineOps*>(dst);
 }
 
-// Parts [PART0, PART1) of the derivative passes: launched as two kernels, the
-// state part (K11, with tangents) and the gradient parts (K12, plain doubles),
-// so that each gets its own register allocation.
-template <int D, int P, int EQ, int PR, int PART0, int PART1>
-__global__ void __launch_bounds__(NT_ELEM) jac_kernel(LineOps ops_arg, MeshParams mp, const double* __restrict__ U,
-                                                      const double* __restrict__ Q, void* __restrict__ K11,
-                                                      void* __restrict__ K12) {
-  using L = JacLayout<D, P, EQ>;
-  constexpr int N1 = L::N1, NG = L::NG, NP = L::NP, NL = L::NL, M = L::M, QW = L::QW;
-  constexpr bool INV = Eq<D, EQ>::INV, VIS = Eq<D, EQ>::VIS;
-  constexpr int NSL = D * P + 1;
-  typedef Dual<1> T1;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* sm = reinterpret_cast<double*>(smem_raw);
-  double* sU = sm + L::oU;
-  double* sQ = sm + L::oQ;
-  double* sX = sm + L::oX;
-  double* sG = sm + L::oG;
-  double* sJ = sm + L::oJ;
-  double* sA = sm + L::oA;
-  double* sFi = sm + L::oFi;
-  double* sFo = sm + L::oFo;
+constexpr int OPS_DOUBLES = (int)(sizeof(LineOps) / sizeof(double));
 
+template <int D, int P>
+__global__ void __launch_bounds__(NT_ELEM) geometry_kernel(LineOps ops_arg, MeshParams mp, double* __restrict__ geo) {
+  using G = GeoShape<D, P>;
+  constexpr int N1 = G::N1, NG = G::NG, NP = G::NP, NL = G::NL;
+  __shared__ double sX[D * NP];
+  __shared__ double sG[D * D * NP];
+  __shared__ double sOps[OPS_DOUBLES];
   const int64_t e = blockIdx.x;
   const int tid = threadIdx.x;
-  const int64_t NN = mp.E * NP;
-  for (int i = tid; i < M * NP; i += NT_ELEM) sU[i] = U[e * M * NP + i];
-  if constexpr (VIS)
-    for (int i = tid; i < QW * NP; i += NT_ELEM) sQ[i] = Q[e * QW * NP + i];
   for (int i = tid; i < D * NP; i += NT_ELEM) sX[i] = mp.xyz[e * D * NP + i];
-  // the 1-D operators are indexed by per-lane positions; from LDS that is a
-  // plain load, from the kernel argument it would need private copies
-  {
-    const double* src = reinterpret_cast<const double*>(&ops_arg);
-    for (int i = tid; i < (int)(sizeof(LineOps) / sizeof(double)); i += NT_ELEM) sm[L::oOps + i] = src[i];
-  }
-  const LineOps& ops = *reinterpret_cast<const LineOps*>(sm + L::oOps);
-  __syncthreads();
+  const LineOps& ops = stage_ops(ops_arg, sOps);
   for (int i = tid; i < D * D * NP; i += NT_ELEM) {
     const int ab = i / NP, node = i % NP;
     const int a = ab / D, b = ab % D;
@@ -108,283 +95,337 @@ __global__ void __launch_bounds__(NT_ELEM) jac_kernel(LineOps ops_arg, MeshParam
     sG[ab * NP + node] = acc;
   }
   __syncthreads();
+  double* out = geo + e * G::REC;
   for (int i = tid; i < NP; i += NT_ELEM) {
-    double G[D][D];
+    double Gm[D][D];
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
-      for (int b = 0; b < D; ++b) G[a][b] = sG[(a * D + b) * NP + i];
-    sJ[i] = -1.0 / det<D>(G);  // row scaling -1/J
+      for (int b = 0; b < D; ++b) Gm[a][b] = sG[(a * D + b) * NP + i];
+    out[G::oJs + i] = -1.0 / det<D>(Gm);
   }
-  __syncthreads();
-
-  constexpr int NPART = VIS ? 1 + D : 1;
-  for (int part = PART0; part < (PART1 < NPART ? PART1 : NPART); ++part) {
-    // self-slot sums over the D directions, one LDS entry per (item, thread):
-    // kept out of registers, which the flux evaluations need
-    double* diag = sm + L::oDiag;
+  for (int it = tid; it < D * NL * NG; it += NT_ELEM) {
+    const int n = it / (NL * NG), l = (it / NG) % NL, g = it % NG;
+    double Gm[D][D], an[D];
 #pragma unroll
-    for (int q = 0; q < L::NITEM; ++q) diag[q * NT_ELEM + tid] = 0.0;
-    const int dq = part - 1;  // derivative direction of q for part > 0
-    for (int n = 0; n < D; ++n) {
-      // ---- volume flux Jacobians at the Gauss points of every direction-n line
-      for (int it = tid; it < NL * NG; it += NT_ELEM) {
-        const int l = it / NG, g = it % NG;
-        double G[D][D], an[D];
+    for (int a = 0; a < D; ++a)
 #pragma unroll
-        for (int a = 0; a < D; ++a)
+      for (int b = 0; b < D; ++b) {
+        double acc = 0.0;
+        if (b == n) {
 #pragma unroll
-          for (int b = 0; b < D; ++b) {
-            double acc = 0.0;
-            if (b == n) {
-#pragma unroll
-              for (int t = 0; t < N1; ++t) acc += ops.Dg[g][t] * sX[a * NP + line_node<D, N1>(n, l, t)];
-            } else {
-#pragma unroll
-              for (int t = 0; t < N1; ++t) acc += ops.I[g][t] * sG[(a * D + b) * NP + line_node<D, N1>(n, l, t)];
-            }
-            G[a][b] = acc;
-          }
-        cofactor_row<D>(G, n, an);
-        if (part == 0) {
-          // the gradient enters the state derivatives as a constant
-          double qd[VIS ? M * D : 1];
-          if constexpr (VIS) {
-#pragma unroll
-            for (int k = 0; k < M * D; ++k) {
-              double acc = 0.0;
-#pragma unroll
-              for (int t = 0; t < N1; ++t) acc += ops.I[g][t] * sQ[k * NP + line_node<D, N1>(n, l, t)];
-              qd[k] = acc;
-            }
-          }
-          // d f / d u, one state component per pass (single-tangent duals);
-          // the gradient is a constant here
-          double ud[M];
-#pragma unroll
-          for (int c = 0; c < M; ++c) {
-            double acc = 0.0;
-#pragma unroll
-            for (int t = 0; t < N1; ++t) acc += ops.I[g][t] * sU[c * NP + line_node<D, N1>(n, l, t)];
-            ud[c] = acc;
-          }
-#pragma unroll 1
-          for (int k = 0; k < M; ++k) {
-            T1 u[M], f[M];
-#pragma unroll
-            for (int c = 0; c < M; ++c) {
-              u[c] = mk<1>(ud[c]);
-              u[c].d[0] = c == k ? 1.0 : 0.0;
-              f[c] = mk<1>(0.0);
-            }
-            if constexpr (VIS) visc_flux_dot_add<D, EQ, T1, double>(u, qd, an, mp.gamma, mp.mu, mp.prandtl, f);
-            if constexpr (INV) {
-              T1 fi[M];
-              euler_flux_dot<D, T1>(u, an, mp.gamma, fi);
-#pragma unroll
-              for (int c = 0; c < M; ++c) f[c] += fi[c];
-            }
-#pragma unroll
-            for (int c = 0; c < M; ++c) sA[((l * NG + g) * M + c) * M + k] = f[c].d[0];
-          }
-        } else if constexpr (VIS) {
-          // d f / d q_{:,dq}: F^vis is linear in q with no q-free term, so
-          // column k is F^vis(u, e_{k,dq}); the inviscid flux has no q
-          double ud[M];
-#pragma unroll
-          for (int c = 0; c < M; ++c) {
-            double acc = 0.0;
-#pragma unroll
-            for (int t = 0; t < N1; ++t) acc += ops.I[g][t] * sU[c * NP + line_node<D, N1>(n, l, t)];
-            ud[c] = acc;
-          }
-#pragma unroll 1
-          for (int k = 0; k < M; ++k) {
-            double ek[M * D], fk[M];
-#pragma unroll
-            for (int j = 0; j < M * D; ++j) ek[j] = (j == k * D + dq) ? 1.0 : 0.0;
-#pragma unroll
-            for (int c = 0; c < M; ++c) fk[c] = 0.0;
-            visc_flux_dot_add<D, EQ, double>(ud, ek, an, mp.gamma, mp.mu, mp.prandtl, fk);
-#pragma unroll
-            for (int c = 0; c < M; ++c) sA[((l * NG + g) * M + c) * M + k] = fk[c];
-          }
-        }
-      }
-      // ---- face flux Jacobians at both ends of every direction-n line
-      for (int it = tid; it < NL * 2; it += NT_ELEM) {
-        const int l = it / 2, s = it % 2;
-        const int nin = line_node<D, N1>(n, l, s ? P : 0);
-        double G[D][D], an[D], nrm[D];
-#pragma unroll
-        for (int a = 0; a < D; ++a)
-#pragma unroll
-          for (int b = 0; b < D; ++b) G[a][b] = sG[(a * D + b) * NP + nin];
-        cofactor_row<D>(G, n, an);
-#pragma unroll
-        for (int d = 0; d < D; ++d) nrm[d] = s ? an[d] : -an[d];
-        const int f = 2 * n + s;
-        const int64_t nb = mp.face_nbr[e * 2 * D + f];
-        const int kind = face_kind(nb);
-        const bool bnd = nb < 0;
-        const int Sp = mp.sw[e * D + n];
-        const int S = s ? Sp : -Sp;
-        double uin[M], uout[M], qin[M * D > 0 ? M * D : 1], qout[M * D > 0 ? M * D : 1];
-#pragma unroll
-        for (int c = 0; c < M; ++c) uin[c] = sU[c * NP + nin];
-        int nd = 0;
-        if (!bnd) {
-          nd = mp.nbr_node[(e * 2 * D + f) * NL + l];
-#pragma unroll
-          for (int c = 0; c < M; ++c) uout[c] = U[(nb * M + c) * NP + nd];
+          for (int t = 0; t < N1; ++t) acc += ops.Dg[g][t] * sX[a * NP + line_node<D, N1>(n, l, t)];
         } else {
-          const double* gb = kind == BC_NEUMANN ? mp.gN : mp.gD;
 #pragma unroll
-          for (int c = 0; c < M; ++c) uout[c] = gb ? gb[((e * 2 * D + f) * M + c) * NL + l] : 0.0;
+          for (int t = 0; t < N1; ++t) acc += ops.I[g][t] * sG[(a * D + b) * NP + line_node<D, N1>(n, l, t)];
         }
-        if constexpr (VIS) {
-          if (part == 0) {  // the gradient derivatives do not involve q itself
-#pragma unroll
-            for (int k = 0; k < M * D; ++k) {
-              qin[k] = sQ[k * NP + nin];
-              qout[k] = (!bnd && S > 0) ? Q[(nb * QW + k) * NP + nd] : qin[k];
-            }
-          }
-        }
-        // derivative with respect to the inside (side 0) and outside (side 1) variable
-        const bool use_out = !bnd && S > 0;  // the side whose viscous flux the switch selects
-        for (int side = 0; side < 2; ++side) {
-          double* dst = (side == 0 ? sFi : sFo) + ((l * 2 + s) * M) * M;
-          if (side == 1 && bnd) {
-#pragma unroll
-            for (int k = 0; k < M * M; ++k) dst[k] = 0.0;
-            continue;
-          }
-          if (part == 0) {
-            double qs[VIS ? M * D : 1];
-#pragma unroll
-            for (int k = 0; k < (VIS ? M * D : 1); ++k) qs[k] = VIS ? (use_out ? qout[k] : qin[k]) : 0.0;
-            // one state component of this side per pass
-#pragma unroll 1
-            for (int k = 0; k < M; ++k) {
-              T1 ti[M], to[M], F[M];
-#pragma unroll
-              for (int c = 0; c < M; ++c) {
-                ti[c] = mk<1>(uin[c]);
-                to[c] = mk<1>(uout[c]);
-                const double seed = c == k ? 1.0 : 0.0;
-                ti[c].d[0] = side == 0 ? seed : 0.0;
-                to[c].d[0] = side == 0 ? 0.0 : seed;
-              }
-              face_flux_point<D, EQ, T1, true, double>(ti, to, qs, nrm, S, kind, mp, F);
-#pragma unroll
-              for (int c = 0; c < M; ++c) dst[c * M + k] = F[c].d[0];
-            }
-          } else if constexpr (VIS) {
-            // only the selected side's gradient enters the flux, linearly (and none on
-            // Neumann faces and slip walls)
-            if ((side == 1) != use_out || kind == BC_NEUMANN || kind == BC_SLIP) {
-#pragma unroll
-              for (int k = 0; k < M * M; ++k) dst[k] = 0.0;
-              continue;
-            }
-            double us[M];
-#pragma unroll
-            for (int c = 0; c < M; ++c) us[c] = use_out ? uout[c] : uin[c];
-#pragma unroll 1
-            for (int k = 0; k < M; ++k) {
-              double ek[M * D], fk[M];
-#pragma unroll
-              for (int j = 0; j < M * D; ++j) ek[j] = (j == k * D + dq) ? 1.0 : 0.0;
-#pragma unroll
-              for (int c = 0; c < M; ++c) fk[c] = 0.0;
-              visc_flux_dot_add<D, EQ, double>(us, ek, nrm, mp.gamma, mp.mu, mp.prandtl, fk);
-#pragma unroll
-              for (int c = 0; c < M; ++c) dst[c * M + k] = fk[c];
-            }
-          }
-        }
+        Gm[a][b] = acc;
       }
-      __syncthreads();
-      // ---- contraction into the block rows
-#pragma unroll 1
-      for (int q = 0; q < L::NITEM; ++q) {
-        const int item = tid + q * NT_ELEM;
-        if (item < NP * M * M) {
-          const int a = item % NP, cc = item / NP;
-          const int c = cc / M, k = cc % M;
-          int l, t;
-          node_line<N1>(a, n, l, t);
-          const double sc = sJ[a];
-          const int64_t gn = e * NP + a;
-          const int Sp = mp.sw[e * D + n];
+    cofactor_row<D>(Gm, n, an);
 #pragma unroll
-          for (int tp = 0; tp < N1; ++tp) {
-            double v = 0.0;
+    for (int d = 0; d < D; ++d) out[G::oAg + it * D + d] = an[d];
+  }
+  for (int it = tid; it < D * NL * 2; it += NT_ELEM) {
+    const int n = it / (NL * 2), l = (it / 2) % NL, s = it % 2;
+    const int nin = line_node<D, N1>(n, l, s ? P : 0);
+    double Gm[D][D], an[D];
 #pragma unroll
-            for (int g = 0; g < NG; ++g) v -= ops.V[t][g] * ops.I[g][tp] * sA[((l * NG + g) * M + c) * M + k];
-            if (tp == P) v += ops.L1[t] * sFi[((l * 2 + 1) * M + c) * M + k];
-            if (tp == 0) v += ops.L0[t] * sFi[((l * 2 + 0) * M + c) * M + k];
-            v *= sc;
-            if (tp == t) {
-              diag[q * NT_ELEM + tid] += v;
-            } else {
-              const int slot = line_slot<D, N1>(n, t, tp);
-              if (part == 0)
-                Store<PR>::put(K11, ((int64_t)(slot * M + c) * M + k) * NN + gn, v);
-              else
-                Store<PR>::put(K12, ((int64_t)(slot * M + c) * (M * D) + k * D + dq) * NN + gn, v);
-            }
-          }
-          if (part == 0) {
-            const double v1 = sc * ops.L1[t] * sFo[((l * 2 + 1) * M + c) * M + k];
-            const double v0 = sc * ops.L0[t] * sFo[((l * 2 + 0) * M + c) * M + k];
-            Store<PR>::put(K11, ((int64_t)((NSL + 2 * n + 1) * M + c) * M + k) * NN + gn, v1);
-            Store<PR>::put(K11, ((int64_t)((NSL + 2 * n + 0) * M + c) * M + k) * NN + gn, v0);
-          } else {
-            const int s = Sp > 0 ? 1 : 0;
-            const double v = sc * (s ? ops.L1[t] : ops.L0[t]) * sFo[((l * 2 + s) * M + c) * M + k];
-            Store<PR>::put(K12, ((int64_t)((NSL + n) * M + c) * (M * D) + k * D + dq) * NN + gn, v);
-          }
-        }
-      }
-      __syncthreads();
-    }
+    for (int a = 0; a < D; ++a)
 #pragma unroll
-    for (int q = 0; q < L::NITEM; ++q) {
-      const int item = tid + q * NT_ELEM;
-      if (item < NP * M * M) {
-        const int a = item % NP, cc = item / NP;
-        const int c = cc / M, k = cc % M;
-        const int slot = a % N1;
-        const int64_t gn = e * NP + a;
-        if (part == 0)
-          Store<PR>::put(K11, ((int64_t)(slot * M + c) * M + k) * NN + gn, diag[q * NT_ELEM + tid]);
-        else
-          Store<PR>::put(K12, ((int64_t)(slot * M + c) * (M * D) + k * D + dq) * NN + gn, diag[q * NT_ELEM + tid]);
-      }
-    }
+      for (int b = 0; b < D; ++b) Gm[a][b] = sG[(a * D + b) * NP + nin];
+    cofactor_row<D>(Gm, n, an);
+#pragma unroll
+    for (int d = 0; d < D; ++d) out[G::oNf + it * D + d] = s ? an[d] : -an[d];
   }
 }
 
-hipError_t launch_jacobian(const DevCtx& dc, const double* U, const double* Q, void* K11, void* K12, int prec) {
-  LDG_DISPATCH(dc, {
-    using L = JacLayout<D, P, EQ>;
-    static_assert(L::bytes <= LDS_PER_CU, "assembly workspace must fit one CU's LDS");
-    LDG_PREC_DISPATCH(prec, {
-      auto k11 = jac_kernel<D, P, EQ, PR, 0, 1>;
-      auto k12 = jac_kernel<D, P, EQ, PR, 1, 1 + D>;
-      if (L::bytes > 65536) {
-        hipError_t err =
-            hipFuncSetAttribute((const void*)k11, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L::bytes);
-        if (err == hipSuccess)
-          err = hipFuncSetAttribute((const void*)k12, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L::bytes);
-        if (err != hipSuccess) return err;
+// Volume flux Jacobians at every Gauss point: work item (e, n, l, g).
+template <int D, int P, int EQ>
+__global__ void __launch_bounds__(256) jac_volume_kernel(LineOps ops_arg, MeshParams mp, const double* __restrict__ geo,
+                                                         const double* __restrict__ U, const double* __restrict__ Q,
+                                                         double* __restrict__ W) {
+  using S = JacShape<D, P, EQ>;
+  using G = GeoShape<D, P>;
+  constexpr int N1 = S::N1, NG = S::NG, NP = S::NP, M = S::M, MM = S::MM, NLG = S::NLG, NPART = S::NPART;
+  constexpr bool INV = Eq<D, EQ>::INV, VIS = Eq<D, EQ>::VIS;
+  constexpr int QW = VIS ? M * D : 1;
+  typedef Dual<1> T1;
+  __shared__ double sOps[OPS_DOUBLES];
+  const LineOps& ops = stage_ops(ops_arg, sOps);
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= mp.E * D * NLG) return;  // no barrier below
+  const int lg = (int)(idx % NLG);
+  const int n = (int)((idx / NLG) % D);
+  const int64_t e = idx / ((int64_t)D * NLG);
+  const int l = lg / NG, g = lg % NG;
+  double an[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) an[d] = geo[e * G::REC + G::oAg + ((int64_t)n * NLG + lg) * D + d];
+  double ud[M];
+#pragma unroll
+  for (int c = 0; c < M; ++c) {
+    double acc = 0.0;
+#pragma unroll
+    for (int t = 0; t < N1; ++t) acc += ops.I[g][t] * U[(e * M + c) * NP + line_node<D, N1>(n, l, t)];
+    ud[c] = acc;
+  }
+  double* out = W + (e * D + n) * (int64_t)NPART * MM * NLG + lg;
+  {
+    double qd[QW];
+    if constexpr (VIS) {
+#pragma unroll
+      for (int k = 0; k < M * D; ++k) {
+        double acc = 0.0;
+#pragma unroll
+        for (int t = 0; t < N1; ++t) acc += ops.I[g][t] * Q[(e * M * D + k) * NP + line_node<D, N1>(n, l, t)];
+        qd[k] = acc;
       }
-      hipLaunchKernelGGL(k11, dim3((unsigned)dc.E), dim3(NT_ELEM), L::bytes, dc.stream, dc.ops, dc.mp, U, Q, K11, K12);
-      if constexpr (Eq<D, EQ>::VIS)
-        hipLaunchKernelGGL(k12, dim3((unsigned)dc.E), dim3(NT_ELEM), L::bytes, dc.stream, dc.ops, dc.mp, U, Q, K11,
-                           K12);
+    }
+    // d f / d u, one state component per pass (the gradient is a constant here)
+#pragma unroll 1
+    for (int k = 0; k < M; ++k) {
+      T1 u[M], f[M];
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        u[c] = mk<1>(ud[c]);
+        u[c].d[0] = c == k ? 1.0 : 0.0;
+        f[c] = mk<1>(0.0);
+      }
+      if constexpr (VIS) visc_flux_dot_add<D, EQ, T1, double>(u, qd, an, mp.gamma, mp.mu, mp.prandtl, f);
+      if constexpr (INV) {
+        T1 fi[M];
+        euler_flux_dot<D, T1>(u, an, mp.gamma, fi);
+#pragma unroll
+        for (int c = 0; c < M; ++c) f[c] += fi[c];
+      }
+#pragma unroll
+      for (int c = 0; c < M; ++c) out[(int64_t)(c * M + k) * NLG] = f[c].d[0];
+    }
+  }
+  if constexpr (VIS) {
+    // d f / d q_{:,dq}: column k is F^vis(u, e_{k,dq}) (no q-free term; no q in the inviscid flux)
+#pragma unroll 1
+    for (int dq = 0; dq < D; ++dq)
+#pragma unroll 1
+      for (int k = 0; k < M; ++k) {
+        double ek[M * D], fk[M];
+#pragma unroll
+        for (int j = 0; j < M * D; ++j) ek[j] = (j == k * D + dq) ? 1.0 : 0.0;
+#pragma unroll
+        for (int c = 0; c < M; ++c) fk[c] = 0.0;
+        visc_flux_dot_add<D, EQ, double>(ud, ek, an, mp.gamma, mp.mu, mp.prandtl, fk);
+#pragma unroll
+        for (int c = 0; c < M; ++c) out[(int64_t)((1 + dq) * MM + c * M + k) * NLG] = fk[c];
+      }
+  }
+}
+
+// Face flux Jacobians at both ends of every line: work item (e, n, l, s);
+// d Fhat / d (inside, outside) for u and for q_{:,d}.
+template <int D, int P, int EQ>
+__global__ void __launch_bounds__(256) jac_face_kernel(MeshParams mp, const double* __restrict__ geo,
+                                                       const double* __restrict__ U, const double* __restrict__ Q,
+                                                       double* __restrict__ W) {
+  using S = JacShape<D, P, EQ>;
+  using G = GeoShape<D, P>;
+  constexpr int N1 = S::N1, NP = S::NP, NL = S::NL, M = S::M, MM = S::MM, NLS = S::NLS, NPART = S::NPART;
+  constexpr bool VIS = Eq<D, EQ>::VIS;
+  constexpr int QW = VIS ? M * D : 1;
+  typedef Dual<1> T1;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= mp.E * D * NLS) return;
+  const int ls = (int)(idx % NLS);
+  const int n = (int)((idx / NLS) % D);
+  const int64_t e = idx / ((int64_t)D * NLS);
+  const int l = ls / 2, s = ls % 2;
+  const int nin = line_node<D, N1>(n, l, s ? P : 0);
+  double nrm[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) nrm[d] = geo[e * G::REC + G::oNf + ((int64_t)n * NLS + ls) * D + d];
+  const int f = 2 * n + s;
+  const int64_t nb = mp.face_nbr[e * 2 * D + f];
+  const int kind = face_kind(nb);
+  const bool bnd = nb < 0;
+  const int Sp = mp.sw[e * D + n];
+  const int Sg = s ? Sp : -Sp;
+  double uin[M], uout[M];
+#pragma unroll
+  for (int c = 0; c < M; ++c) uin[c] = U[(e * M + c) * NP + nin];
+  int nd = 0;
+  if (!bnd) {
+    nd = mp.nbr_node[(e * 2 * D + f) * NL + l];
+#pragma unroll
+    for (int c = 0; c < M; ++c) uout[c] = U[(nb * M + c) * NP + nd];
+  } else {
+    const double* gb = kind == BC_NEUMANN ? mp.gN : mp.gD;
+#pragma unroll
+    for (int c = 0; c < M; ++c) uout[c] = gb ? gb[((e * 2 * D + f) * M + c) * NL + l] : 0.0;
+  }
+  const bool use_out = !bnd && Sg > 0;  // the side whose viscous flux the switch selects
+  // record of this line end: [part][side][c][c'] with the line-end index fastest
+  double* out = W + (e * D + n) * (int64_t)NPART * 2 * MM * NLS + ls;
+  {
+    double qs[QW];
+    if constexpr (VIS) {
+#pragma unroll
+      for (int k = 0; k < M * D; ++k)
+        qs[k] = use_out ? Q[(nb * M * D + k) * NP + nd] : Q[(e * M * D + k) * NP + nin];
+    }
+#pragma unroll 1
+    for (int side = 0; side < 2; ++side) {
+      if (side == 1 && bnd) {
+#pragma unroll
+        for (int k = 0; k < MM; ++k) out[(int64_t)(MM + k) * NLS] = 0.0;
+        continue;
+      }
+#pragma unroll 1
+      for (int k = 0; k < M; ++k) {
+        T1 ti[M], to[M], F[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          ti[c] = mk<1>(uin[c]);
+          to[c] = mk<1>(uout[c]);
+          const double seed = c == k ? 1.0 : 0.0;
+          ti[c].d[0] = side == 0 ? seed : 0.0;
+          to[c].d[0] = side == 0 ? 0.0 : seed;
+        }
+        face_flux_point<D, EQ, T1, true, double>(ti, to, qs, nrm, Sg, kind, mp, F);
+#pragma unroll
+        for (int c = 0; c < M; ++c) out[(int64_t)(side * MM + c * M + k) * NLS] = F[c].d[0];
+      }
+    }
+  }
+  if constexpr (VIS) {
+    // only the selected side's gradient enters the flux, linearly (none on Neumann faces and slip walls)
+    const bool none = kind == BC_NEUMANN || kind == BC_SLIP;
+    double us[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) us[c] = use_out ? uout[c] : uin[c];
+#pragma unroll 1
+    for (int dq = 0; dq < D; ++dq)
+#pragma unroll 1
+      for (int k = 0; k < M; ++k) {
+        double ek[M * D], fk[M];
+#pragma unroll
+        for (int j = 0; j < M * D; ++j) ek[j] = (j == k * D + dq) ? 1.0 : 0.0;
+#pragma unroll
+        for (int c = 0; c < M; ++c) fk[c] = 0.0;
+        if (!none) visc_flux_dot_add<D, EQ, double>(us, ek, nrm, mp.gamma, mp.mu, mp.prandtl, fk);
+        double* o = out + (int64_t)((1 + dq) * 2 * MM) * NLS;
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          o[(int64_t)(0 * MM + c * M + k) * NLS] = use_out ? 0.0 : fk[c];
+          o[(int64_t)(1 * MM + c * M + k) * NLS] = use_out ? fk[c] : 0.0;
+        }
+      }
+  }
+}
+
+// Contraction into the block rows: one work item per (element, part,
+// component pair, row node), the node fastest so that a wavefront writes
+// consecutive nodes of every [slot][c][c'][node] row.  The point Jacobians of
+// a line are read by the p + 1 work items of its nodes, next to each other in
+// the wavefront (cache hits after the first); the self slot sums the D
+// directions in a register.
+template <int D, int P, int EQ, int PR>
+__global__ void __launch_bounds__(256) jac_contract_kernel(LineOps ops_arg, MeshParams mp,
+                                                           const double* __restrict__ geo,
+                                                           const double* __restrict__ Wv,
+                                                           const double* __restrict__ Wf, void* __restrict__ K11,
+                                                           void* __restrict__ K12) {
+  using S = JacShape<D, P, EQ>;
+  using G = GeoShape<D, P>;
+  constexpr int N1 = S::N1, NG = S::NG, NP = S::NP, M = S::M, MM = S::MM, NLG = S::NLG, NLS = S::NLS;
+  constexpr int NPART = S::NPART, NSL = D * P + 1;
+  __shared__ double sOps[OPS_DOUBLES];
+  const LineOps& ops = stage_ops(ops_arg, sOps);
+  const int64_t NN = mp.E * NP;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= NN * NPART * MM) return;  // no barrier below
+  const int a = (int)(idx % NP);
+  const int cc = (int)((idx / NP) % MM);
+  const int part = (int)((idx / ((int64_t)NP * MM)) % NPART);
+  const int64_t e = idx / ((int64_t)NP * MM * NPART);
+  const int c = cc / M, k = cc % M;
+  const int64_t gn = e * NP + a;
+  const double sc = geo[e * G::REC + G::oJs + a];
+  double diag = 0.0;
+#pragma unroll 1
+  for (int n = 0; n < D; ++n) {
+    int l, t;
+    node_line<N1>(a, n, l, t);
+    const double* Ar = Wv + (((e * D + n) * NPART + part) * MM + cc) * (int64_t)NLG + l * NG;
+    const double* Fr = Wf + ((e * D + n) * NPART + part) * (int64_t)2 * MM * NLS + cc * NLS + l * 2;
+    double Vt[NG];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) Vt[g] = ops.V[t][g] * Ar[g];
+    const double fin0 = Fr[0], fin1 = Fr[1], fo0 = Fr[MM * NLS], fo1 = Fr[MM * NLS + 1];
+#pragma unroll
+    for (int tp = 0; tp < N1; ++tp) {
+      double v = 0.0;
+#pragma unroll
+      for (int g = 0; g < NG; ++g) v -= Vt[g] * ops.I[g][tp];
+      if (tp == P) v += ops.L1[t] * fin1;
+      if (tp == 0) v += ops.L0[t] * fin0;
+      v *= sc;
+      if (tp == t) {
+        diag += v;
+      } else {
+        const int slot = slot_of<N1>(n, t, tp, t);
+        if (part == 0)
+          Store<PR>::put(K11, ((int64_t)(slot * M + c) * M + k) * NN + gn, v);
+        else
+          Store<PR>::put(K12, ((int64_t)(slot * M + c) * (M * D) + k * D + (part - 1)) * NN + gn, v);
+      }
+    }
+    if (part == 0) {
+      Store<PR>::put(K11, ((int64_t)((NSL + 2 * n + 1) * M + c) * M + k) * NN + gn, sc * ops.L1[t] * fo1);
+      Store<PR>::put(K11, ((int64_t)((NSL + 2 * n + 0) * M + c) * M + k) * NN + gn, sc * ops.L0[t] * fo0);
+    } else {
+      const int s = mp.sw[e * D + n] > 0 ? 1 : 0;
+      const double v = sc * (s ? ops.L1[t] * fo1 : ops.L0[t] * fo0);
+      Store<PR>::put(K12, ((int64_t)((NSL + n) * M + c) * (M * D) + k * D + (part - 1)) * NN + gn, v);
+    }
+  }
+  const int slot = a % N1;
+  if (part == 0)
+    Store<PR>::put(K11, ((int64_t)(slot * M + c) * M + k) * NN + gn, diag);
+  else
+    Store<PR>::put(K12, ((int64_t)(slot * M + c) * (M * D) + k * D + (part - 1)) * NN + gn, diag);
+}
+
+size_t jacobian_geometry_doubles(const DevCtx& dc) {
+  const size_t rec = (size_t)dc.D * dc.NL * dc.NG * dc.D + (size_t)dc.D * dc.NL * 2 * dc.D + dc.NP;
+  return (size_t)dc.E * rec;
+}
+
+size_t jacobian_workspace_doubles(const DevCtx& dc) {
+  const size_t npart = dc.EQ != EQ_EULER ? 1 + dc.D : 1, mm = (size_t)dc.M * dc.M;
+  return (size_t)dc.E * dc.D * npart * mm * ((size_t)dc.NL * dc.NG + 2 * (size_t)dc.NL * 2);
+}
+
+hipError_t launch_jacobian_geometry(const DevCtx& dc, double* geo) {
+  LDG_DISPATCH(dc, {
+    hipLaunchKernelGGL((geometry_kernel<D, P>), dim3((unsigned)dc.E), dim3(NT_ELEM), 0, dc.stream, dc.ops, dc.mp, geo);
+    return hipGetLastError();
+  })
+}
+
+hipError_t launch_jacobian(const DevCtx& dc, const double* U, const double* Q, void* K11, void* K12, int prec,
+                           const double* geo, double* work) {
+  LDG_DISPATCH(dc, {
+    using S = JacShape<D, P, EQ>;
+    double* Wv = work;
+    double* Wf = work + dc.E * S::VOL;
+    const int64_t nv = dc.E * D * S::NLG, nf = dc.E * D * S::NLS;
+    const int64_t nc = dc.E * (int64_t)S::NP * S::NPART * S::MM;
+    hipLaunchKernelGGL((jac_volume_kernel<D, P, EQ>), dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, dc.stream,
+                       dc.ops, dc.mp, geo, U, Q, Wv);
+    hipLaunchKernelGGL((jac_face_kernel<D, P, EQ>), dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, dc.stream,
+                       dc.mp, geo, U, Q, Wf);
+    LDG_PREC_DISPATCH(prec, {
+      hipLaunchKernelGGL((jac_contract_kernel<D, P, EQ, PR>), dim3((unsigned)((nc + 255) / 256)), dim3(256), 0,
+                         dc.stream, dc.ops, dc.mp, geo, Wv, Wf, K11, K12);
       return hipGetLastError();
     })
   })

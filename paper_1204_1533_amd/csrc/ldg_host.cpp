@@ -82,7 +82,7 @@ void ldg_destroy(ldg_ctx c) {
   void* ptrs[] = {c->d_xyz, c->d_face_nbr, c->d_nbr_node, c->d_sw, c->d_gD, c->d_gN, c->d_S, c->d_Q, c->d_W, c->d_W2,
                   c->d_K11, c->d_K12, c->d_F, c->d_Fem, c->d_Ua, c->d_Qa, c->d_V, c->d_Z, c->d_R, c->d_G, c->d_x, c->d_r, c->d_z,
                   c->d_tmp, c->d_Un, c->d_partial, c->d_h, c->d_Uold, c->d_st_Un, c->d_st_comb, c->d_st_K,
-                  c->d_K21w, c->d_Dense};
+                  c->d_K21w, c->d_Dense, c->d_geo, c->d_Jwork};
   for (void* p : ptrs)
     if (p) hipFree(p);
   learned_free(c);
@@ -308,7 +308,13 @@ static ldg_status assemble(ldg_ctx c, const double* U, double alpha, double gamm
   HIPCK(c, hipMemcpyAsync(c->d_Ua, U, sizeof(double) * c->ndof, hipMemcpyDeviceToDevice, dc.stream));
   const bool vis = dc.EQ != LDG_EULER;
   if (vis) HIPCK(c, launch_gradient(dc, U, c->d_Qa, false));
-  HIPCK(c, launch_jacobian(dc, U, vis ? c->d_Qa : nullptr, c->d_K11, c->d_K12, prec));
+  if (!c->d_geo) {
+    // Gauss-point metrics, line-end normals and -1/J: fixed by the mesh
+    TRY(dev_alloc(c, &c->d_geo, jacobian_geometry_doubles(dc)));
+    HIPCK(c, launch_jacobian_geometry(dc, c->d_geo));
+  }
+  TRY(grow(c, (void**)&c->d_Jwork, &c->capJwork, sizeof(double) * jacobian_workspace_doubles(dc)));
+  HIPCK(c, launch_jacobian(dc, U, vis ? c->d_Qa : nullptr, c->d_K11, c->d_K12, prec, c->d_geo, c->d_Jwork));
   const bool block_lu = c->precond_kind == LDG_PRECOND_BLOCK_LU;
   const bool keep = !block_lu && (c->learned_collect || (c->net && c->learned_enabled));
   if (keep) TRY(dev_alloc(c, &c->d_At, nF));

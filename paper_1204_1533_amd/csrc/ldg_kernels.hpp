@@ -60,7 +60,13 @@ hipError_t launch_k21_weights(const DevCtx& c, double* Wt);
 hipError_t launch_k21_apply(const DevCtx& c, const double* Wt, const double* x, double* w);
 
 // Jacobian blocks; prec: 0 f64, 1 f32, 2 bf16.  Layout [slot][row comp][col comp][E*Np].
-hipError_t launch_jacobian(const DevCtx& c, const double* U, const double* Q, void* K11, void* K12, int prec);
+// Jacobian blocks in three launches: geometry record per element (once per
+// context), point flux Jacobians into a workspace, contraction into the blocks
+size_t jacobian_geometry_doubles(const DevCtx& c);
+size_t jacobian_workspace_doubles(const DevCtx& c);
+hipError_t launch_jacobian_geometry(const DevCtx& c, double* geo);
+hipError_t launch_jacobian(const DevCtx& c, const double* U, const double* Q, void* K11, void* K12, int prec,
+                           const double* geo, double* work);
 
 // y = alpha x - gamma (K11 x + K12 w), w = D_hom(x) given.
 hipError_t launch_jacvec(const DevCtx& c, const void* K11, const void* K12, int prec, double alpha, double gamma,
