@@ -323,10 +323,12 @@ __global__ void __launch_bounds__(256) jac_face_kernel(MeshParams mp, const doub
 
 // Contraction into the block rows: one work item per (element, part,
 // component pair, row node), the node fastest so that a wavefront writes
-// consecutive nodes of every [slot][c][c'][node] row.  The point Jacobians of
-// a line are read by the p + 1 work items of its nodes, next to each other in
-// the wavefront (cache hits after the first); the self slot sums the D
-// directions in a register.
+// consecutive nodes of every [slot][c][c'][node] row.  Grid: x over the
+// element's (component pair, node) items, y over elements, z over parts, so
+// element and part are uniform in a workgroup.  The point Jacobians of a line
+// are read by the p + 1 work items of its nodes, next to each other in the
+// wavefront (cache hits after the first); the self slot sums the D directions
+// in a register.
 template <int D, int P, int EQ, int PR>
 __global__ void __launch_bounds__(256) jac_contract_kernel(LineOps ops_arg, MeshParams mp,
                                                            const double* __restrict__ geo,
@@ -337,61 +339,56 @@ __global__ void __launch_bounds__(256) jac_contract_kernel(LineOps ops_arg, Mesh
   using G = GeoShape<D, P>;
   constexpr int N1 = S::N1, NG = S::NG, NP = S::NP, M = S::M, MM = S::MM, NLG = S::NLG, NLS = S::NLS;
   constexpr int NPART = S::NPART, NSL = D * P + 1;
+  using T = typename Store<PR>::type;
   __shared__ double sOps[OPS_DOUBLES];
   const LineOps& ops = stage_ops(ops_arg, sOps);
   const int64_t NN = mp.E * NP;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= NN * NPART * MM) return;  // no barrier below
-  const int a = (int)(idx % NP);
-  const int cc = (int)((idx / NP) % MM);
-  const int part = (int)((idx / ((int64_t)NP * MM)) % NPART);
-  const int64_t e = idx / ((int64_t)NP * MM * NPART);
+  const int item = blockIdx.x * blockDim.x + threadIdx.x;
+  if (item >= NP * MM) return;  // no barrier below
+  const int a = item % NP, cc = item / NP;
+  const int part = blockIdx.z;
   const int c = cc / M, k = cc % M;
-  const int64_t gn = e * NP + a;
-  const double sc = geo[e * G::REC + G::oJs + a];
-  double diag = 0.0;
+  // the block row's first row of K11 (slot, c, k) or K12 (slot, c, (k, dq)), and the slot stride
+  const int64_t row0 = part == 0 ? (int64_t)(c * M + k) : (int64_t)c * (M * D) + k * D + (part - 1);
+  const int64_t slot_stride = (part == 0 ? (int64_t)MM : (int64_t)MM * D) * NN;
+  T* Kp = (T*)(part == 0 ? K11 : K12) + row0 * NN;
+  for (int64_t e = blockIdx.y; e < mp.E; e += gridDim.y) {
+    const int64_t gn = e * NP + a;
+    const double sc = geo[e * G::REC + G::oJs + a];
+    double diag = 0.0;
 #pragma unroll 1
-  for (int n = 0; n < D; ++n) {
-    int l, t;
-    node_line<N1>(a, n, l, t);
-    const double* Ar = Wv + (((e * D + n) * NPART + part) * MM + cc) * (int64_t)NLG + l * NG;
-    const double* Fr = Wf + ((e * D + n) * NPART + part) * (int64_t)2 * MM * NLS + cc * NLS + l * 2;
-    double Vt[NG];
+    for (int n = 0; n < D; ++n) {
+      int l, t;
+      node_line<N1>(a, n, l, t);
+      const double* Ar = Wv + ((e * D + n) * NPART + part) * (int64_t)MM * NLG + cc * NLG + l * NG;
+      const double* Fr = Wf + ((e * D + n) * NPART + part) * (int64_t)2 * MM * NLS + cc * NLS + l * 2;
+      double Vt[NG];
 #pragma unroll
-    for (int g = 0; g < NG; ++g) Vt[g] = ops.V[t][g] * Ar[g];
-    const double fin0 = Fr[0], fin1 = Fr[1], fo0 = Fr[MM * NLS], fo1 = Fr[MM * NLS + 1];
+      for (int g = 0; g < NG; ++g) Vt[g] = ops.V[t][g] * Ar[g];
+      const double fin0 = Fr[0], fin1 = Fr[1], fo0 = Fr[MM * NLS], fo1 = Fr[MM * NLS + 1];
 #pragma unroll
-    for (int tp = 0; tp < N1; ++tp) {
-      double v = 0.0;
+      for (int tp = 0; tp < N1; ++tp) {
+        double v = 0.0;
 #pragma unroll
-      for (int g = 0; g < NG; ++g) v -= Vt[g] * ops.I[g][tp];
-      if (tp == P) v += ops.L1[t] * fin1;
-      if (tp == 0) v += ops.L0[t] * fin0;
-      v *= sc;
-      if (tp == t) {
-        diag += v;
-      } else {
-        const int slot = slot_of<N1>(n, t, tp, t);
-        if (part == 0)
-          Store<PR>::put(K11, ((int64_t)(slot * M + c) * M + k) * NN + gn, v);
+        for (int g = 0; g < NG; ++g) v -= Vt[g] * ops.I[g][tp];
+        if (tp == P) v += ops.L1[t] * fin1;
+        if (tp == 0) v += ops.L0[t] * fin0;
+        v *= sc;
+        if (tp == t)
+          diag += v;
         else
-          Store<PR>::put(K12, ((int64_t)(slot * M + c) * (M * D) + k * D + (part - 1)) * NN + gn, v);
+          Store<PR>::put(Kp, slot_of<N1>(n, t, tp, t) * slot_stride + gn, v);
+      }
+      if (part == 0) {
+        Store<PR>::put(Kp, (NSL + 2 * n + 1) * slot_stride + gn, sc * ops.L1[t] * fo1);
+        Store<PR>::put(Kp, (NSL + 2 * n + 0) * slot_stride + gn, sc * ops.L0[t] * fo0);
+      } else {
+        const int s = mp.sw[e * D + n] > 0 ? 1 : 0;
+        Store<PR>::put(Kp, (NSL + n) * slot_stride + gn, sc * (s ? ops.L1[t] * fo1 : ops.L0[t] * fo0));
       }
     }
-    if (part == 0) {
-      Store<PR>::put(K11, ((int64_t)((NSL + 2 * n + 1) * M + c) * M + k) * NN + gn, sc * ops.L1[t] * fo1);
-      Store<PR>::put(K11, ((int64_t)((NSL + 2 * n + 0) * M + c) * M + k) * NN + gn, sc * ops.L0[t] * fo0);
-    } else {
-      const int s = mp.sw[e * D + n] > 0 ? 1 : 0;
-      const double v = sc * (s ? ops.L1[t] * fo1 : ops.L0[t] * fo0);
-      Store<PR>::put(K12, ((int64_t)((NSL + n) * M + c) * (M * D) + k * D + (part - 1)) * NN + gn, v);
-    }
+    Store<PR>::put(Kp, (a % N1) * slot_stride + gn, diag);
   }
-  const int slot = a % N1;
-  if (part == 0)
-    Store<PR>::put(K11, ((int64_t)(slot * M + c) * M + k) * NN + gn, diag);
-  else
-    Store<PR>::put(K12, ((int64_t)(slot * M + c) * (M * D) + k * D + (part - 1)) * NN + gn, diag);
 }
 
 size_t jacobian_geometry_doubles(const DevCtx& dc) {
@@ -418,14 +415,15 @@ hipError_t launch_jacobian(const DevCtx& dc, const double* U, const double* Q, v
     double* Wv = work;
     double* Wf = work + dc.E * S::VOL;
     const int64_t nv = dc.E * D * S::NLG, nf = dc.E * D * S::NLS;
-    const int64_t nc = dc.E * (int64_t)S::NP * S::NPART * S::MM;
+    const dim3 cgrid((unsigned)((S::NP * S::MM + 255) / 256), (unsigned)(dc.E < 65535 ? dc.E : 65535),
+                     (unsigned)S::NPART);
     hipLaunchKernelGGL((jac_volume_kernel<D, P, EQ>), dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, dc.stream,
                        dc.ops, dc.mp, geo, U, Q, Wv);
     hipLaunchKernelGGL((jac_face_kernel<D, P, EQ>), dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, dc.stream,
                        dc.mp, geo, U, Q, Wf);
     LDG_PREC_DISPATCH(prec, {
-      hipLaunchKernelGGL((jac_contract_kernel<D, P, EQ, PR>), dim3((unsigned)((nc + 255) / 256)), dim3(256), 0,
-                         dc.stream, dc.ops, dc.mp, geo, Wv, Wf, K11, K12);
+      hipLaunchKernelGGL((jac_contract_kernel<D, P, EQ, PR>), cgrid, dim3(256), 0, dc.stream, dc.ops, dc.mp, geo,
+                         Wv, Wf, K11, K12);
       return hipGetLastError();
     })
   })

@@ -25,6 +25,7 @@
 //           the U diagonal block.
 // apply:    forward / backward block substitution over the same levels.
 #include <type_traits>
+#include <utility>
 
 #include "ldg_dispatch.hpp"
 #include "ldg_kernels.hpp"
@@ -586,15 +587,16 @@ struct ApplyShape {
 
 // z = (L U)^{-1} r element by element, by level: rows with equal a_0 + .. +
 // a_{D-1} are independent.  The work items of an element take the rows of one
-// level at a time (one row each: node a, component c); the factor rows are
-// stored in level order, so a level's rows are one contiguous run read with
-// 8- to 32-byte loads.  y_a = r_a - sum_{k < a} L_ak y_k, then
-// z_a = U_aa^{-1} (y_a - sum_{j > a} U_aj z_j) with the inverse diagonal block
-// stored in the diagonal slot.  y and t live in LDS node-major (the m values
-// of a node in one 16-byte aligned run, read with 16-byte loads).  A row is
-// loaded when its level starts, not one level ahead: the loads of the other
-// resident workgroups hide the latency, and registers for a second row would
-// halve the workgroups per CU.
+// level at a time (one row each: node a, component c).  A row of level L
+// stores its L left blocks first, then the diagonal block (the inverse of the
+// U diagonal block), then the D p - L right blocks, so with the levels
+// unrolled at compile time the forward sweep at level L reads exactly the
+// row's first L blocks and the backward sweep the rest, each once, with no
+// masked slots:
+//   y_a = r_a - sum_{left k} L_ak y_k,   z_a = U_aa^{-1} (y_a - sum_{right j} U_aj z_j).
+// The factor rows of a level are one contiguous run read 4 entries at a time;
+// y and t live in LDS node-major (the m values of a node in one 16-byte
+// aligned run, read with 16-byte loads).
 template <int M>
 struct NodeRun {
   static constexpr int YS = (M + 1) / 2 * 2;  // doubles per node in LDS
@@ -609,6 +611,132 @@ struct NodeRun {
   }
 };
 
+template <int D, int P>
+__device__ __forceinline__ void node_coords(int a, int* cd) {
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    cd[d] = a % (P + 1);
+    a /= P + 1;
+  }
+}
+
+template <int D, int P, int EQ, int FP, int L>
+__device__ __forceinline__ void apply_forward_level(const LevelOrder& ord, int64_t e, bool live, int lane,
+                                                    const void* F, double* y) {
+  using S = FacShape<D, P, EQ>;
+  constexpr int N1 = P + 1, M = S::M, NR = S::NR, NJP = S::NJP, YS = NodeRun<M>::YS;
+  constexpr int NCH = (L * M + 3) / 4;  // chunks holding the L left blocks
+  const int row = ord.off[L] * M + lane;
+  if (live && row < ord.off[L + 1] * M) {
+    RowRegs<FP, 4 * NCH> f;
+    f.load(F, fac_index(e, row, 0, NR, NJP), NR);
+    const int a = ord.node[row / M], c = row % M;
+    // the u-th left block sits on the line of the direction whose positions u falls in:
+    // column = base_d + u stride_d with thresholds hi_d (positions before direction d + 1)
+    int base[D], hi[D];
+    {
+      int cd[D];
+      node_coords<D, P>(a, cd);
+      int before = 0, stride = 1;
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        base[d] = a - (cd[d] + before) * stride;
+        before += cd[d];
+        hi[d] = before;
+        stride *= N1;
+      }
+    }
+    double acc = y[a * YS + c];
+#pragma unroll
+    for (int u = 0; u < L; ++u) {
+      int col = base[D - 1] + u * ipow(N1, D - 1);
+#pragma unroll
+      for (int d = D - 2; d >= 0; --d) col = u < hi[d] ? base[d] + u * ipow(N1, d) : col;
+      NodeRun<M> yk;
+      yk.load(y + col * YS);
+      double tt = 0.0;  // one block at a time: short dependency chains
+#pragma unroll
+      for (int q = 0; q < M; ++q) tt += f.get(u * M + q) * yk.v[q];
+      acc -= tt;
+      // blocks one after another: hoisting every block's loads would hold them all in registers
+      // and cost resident wavefronts; the other wavefronts hide the LDS latency
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    y[a * YS + c] = acc;
+  }
+  __syncthreads();
+}
+
+template <int D, int P, int EQ, int FP, int L>
+__device__ __forceinline__ void apply_backward_level(const LevelOrder& ord, int64_t e, bool live, int lane,
+                                                     const void* F, double* y, double* t) {
+  using S = FacShape<D, P, EQ>;
+  constexpr int N1 = P + 1, M = S::M, NR = S::NR, NJP = S::NJP, YS = NodeRun<M>::YS;
+  constexpr int NUP = D * P - L;            // right blocks
+  constexpr int C0 = (L * M) / 4;           // first chunk holding the diagonal block
+  constexpr int NCH = NJP / 4 - C0;
+  constexpr int OFF = 4 * C0;               // entry held in register 0
+  const int row = ord.off[L] * M + lane;
+  const bool act = live && row < ord.off[L + 1] * M;
+  RowRegs<FP, 4 * NCH> f;
+  int a = 0, c = 0;
+  if (act) {
+    f.load(F, fac_index(e, row, OFF, NR, NJP), NR);
+    a = ord.node[row / M];
+    c = row % M;
+    // the u-th right block: column = base_d + u stride_d, d the direction whose positions u falls in
+    int base[D], hi[D];
+    {
+      int cd[D];
+      node_coords<D, P>(a, cd);
+      int before = 0, stride = 1;
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        base[d] = a + (1 - before) * stride;
+        before += P - cd[d];
+        hi[d] = before;
+        stride *= N1;
+      }
+    }
+    double acc = y[a * YS + c];
+#pragma unroll
+    for (int u = 0; u < NUP; ++u) {
+      int col = base[D - 1] + u * ipow(N1, D - 1);
+#pragma unroll
+      for (int d = D - 2; d >= 0; --d) col = u < hi[d] ? base[d] + u * ipow(N1, d) : col;
+      NodeRun<M> zj;
+      zj.load(y + col * YS);
+      double tt = 0.0;
+#pragma unroll
+      for (int q = 0; q < M; ++q) tt += f.get((L + 1 + u) * M + q - OFF) * zj.v[q];
+      acc -= tt;
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    t[a * YS + c] = acc;
+  }
+  __syncthreads();
+  if (act) {
+    NodeRun<M> ta;
+    ta.load(t + a * YS);
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < M; ++q) v += f.get(L * M + q - OFF) * ta.v[q];
+    y[a * YS + c] = v;
+  }
+  __syncthreads();
+}
+
+template <int D, int P, int EQ, int FP, int... Ls>
+__device__ __forceinline__ void apply_forward_all(std::integer_sequence<int, Ls...>, const LevelOrder& ord, int64_t e,
+                                                  bool live, int lane, const void* F, double* y) {
+  (apply_forward_level<D, P, EQ, FP, Ls + 1>(ord, e, live, lane, F, y), ...);
+}
+template <int D, int P, int EQ, int FP, int... Ls>
+__device__ __forceinline__ void apply_backward_all(std::integer_sequence<int, Ls...>, const LevelOrder& ord, int64_t e,
+                                                   bool live, int lane, const void* F, double* y, double* t) {
+  (apply_backward_level<D, P, EQ, FP, D * P - Ls>(ord, e, live, lane, F, y, t), ...);
+}
+
 template <int D, int P, int EQ, int FP>
 __global__ void __launch_bounds__((ApplyShape<D, P, EQ>::NT)) apply_kernel(LevelOrder ord, int64_t E,
                                                                           const void* __restrict__ F,
@@ -616,8 +744,8 @@ __global__ void __launch_bounds__((ApplyShape<D, P, EQ>::NT)) apply_kernel(Level
                                                                           double* __restrict__ z) {
   using S = FacShape<D, P, EQ>;
   using A = ApplyShape<D, P, EQ>;
-  constexpr int N1 = P + 1, NP = S::NP, M = S::M, NSL = S::NSL, NR = S::NR, NJP = S::NJP;
-  constexpr int TPE = A::TPE, EPB = A::EPB, NL = D * P, YS = NodeRun<M>::YS;
+  constexpr int NP = S::NP, M = S::M, NR = S::NR;
+  constexpr int TPE = A::TPE, EPB = A::EPB, YS = NodeRun<M>::YS;
   __shared__ __align__(16) double sy[EPB * NP * YS];
   __shared__ __align__(16) double st[EPB * NP * YS];
   const int tid = threadIdx.x;
@@ -629,70 +757,9 @@ __global__ void __launch_bounds__((ApplyShape<D, P, EQ>::NT)) apply_kernel(Level
   if (live)
     for (int i = lane; i < NR; i += TPE) y[(i % NP) * YS + i / NP] = r[e * NR + i];
   __syncthreads();
-  RowRegs<FP, NJP> f;
-  // forward sweep over levels 1..NL (level 0 has no lower entries)
-  for (int L = 1; L <= NL; ++L) {
-    const int row = ord.off[L] * M + lane;
-    if (live && row < ord.off[L + 1] * M) {
-      f.load(F, fac_index(e, row, 0, NR, NJP), NR);
-      const int a = ord.node[row / M], c = row % M;
-      double acc = y[a * YS + c];
-#pragma unroll
-      for (int s = 0; s < NSL; ++s) {
-        const int k = slot_col<D, P>(a, s);
-        if (k < a) {
-          NodeRun<M> yk;
-          yk.load(y + k * YS);
-          double tt = 0.0;  // one block row at a time: short dependency chains
-#pragma unroll
-          for (int q = 0; q < M; ++q) tt += f.get(s * M + q) * yk.v[q];
-          acc -= tt;
-        }
-      }
-      y[a * YS + c] = acc;
-    }
-    __syncthreads();
-  }
-  // backward sweep over levels NL..0
-  for (int L = NL; L >= 0; --L) {
-    const int row = ord.off[L] * M + lane;
-    const bool act = live && row < ord.off[L + 1] * M;
-    int a = 0, c = 0;
-    if (act) {
-      f.load(F, fac_index(e, row, 0, NR, NJP), NR);
-      a = ord.node[row / M];
-      c = row % M;
-      double acc = y[a * YS + c];
-#pragma unroll
-      for (int s = 0; s < NSL; ++s) {
-        const int j = slot_col<D, P>(a, s);
-        if (j > a) {
-          NodeRun<M> zj;
-          zj.load(y + j * YS);
-          double tt = 0.0;
-#pragma unroll
-          for (int q = 0; q < M; ++q) tt += f.get(s * M + q) * zj.v[q];
-          acc -= tt;
-        }
-      }
-      t[a * YS + c] = acc;
-    }
-    __syncthreads();
-    if (act) {
-      const int self = a % N1;
-      NodeRun<M> ta;
-      ta.load(t + a * YS);
-      double v = 0.0;
-#pragma unroll
-      for (int s = 0; s < N1; ++s)
-        if (s == self) {
-#pragma unroll
-          for (int q = 0; q < M; ++q) v += f.get(s * M + q) * ta.v[q];
-        }
-      y[a * YS + c] = v;
-    }
-    __syncthreads();
-  }
+  // forward over levels 1 .. D p (level 0 has no left blocks), backward over D p .. 0
+  apply_forward_all<D, P, EQ, FP>(std::make_integer_sequence<int, D * P>{}, ord, e, live, lane, F, y);
+  apply_backward_all<D, P, EQ, FP>(std::make_integer_sequence<int, D * P + 1>{}, ord, e, live, lane, F, y, t);
   if (live)
     for (int i = lane; i < NR; i += TPE) z[e * NR + i] = y[(i % NP) * YS + i / NP];
 }
@@ -700,7 +767,7 @@ __global__ void __launch_bounds__((ApplyShape<D, P, EQ>::NT)) apply_kernel(Level
 // element-major factors [E Np][slot][c][c'] -> apply layout (zero padding)
 template <int PIN, int POUT>
 __global__ void em_to_fac_kernel(LevelOrder ord, const void* __restrict__ in, void* __restrict__ out, int64_t E,
-                                 int NP, int M, int NSL) {
+                                 int NP, int M, int NSL, int D, int P) {
   const int NR = NP * M, NJ = NSL * M, NJP = (NJ + 3) / 4 * 4;
   const int64_t total = E * (int64_t)NJP * NR;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
@@ -713,7 +780,8 @@ __global__ void em_to_fac_kernel(LevelOrder ord, const void* __restrict__ in, vo
     const int j = ch * 4 + jj;
     double v = 0.0;
     if (j < NJ) {
-      const int a = ord.node[rr / M], c = rr % M, slot = j / M, cp = j % M;
+      const int a = ord.node[rr / M], c = rr % M, cp = j % M;
+      const int slot = row_slot_at(D, P, a, j / M);
       v = Store<PIN>::get(in, ((e * NP + a) * NSL + slot) * (int64_t)(M * M) + c * M + cp);
     }
     Store<POUT>::put(out, i, v);
@@ -723,7 +791,7 @@ __global__ void em_to_fac_kernel(LevelOrder ord, const void* __restrict__ in, vo
 // apply layout -> FP64 [E][Np][slot][c][c'] (the exchange layout of ldg_export_operators)
 template <int PIN>
 __global__ void fac_to_em64_kernel(LevelOrder ord, const void* __restrict__ in, double* __restrict__ out, int64_t E,
-                                   int NP, int M, int NSL) {
+                                   int NP, int M, int NSL, int D, int P) {
   const int NR = NP * M, NJP = (NSL * M + 3) / 4 * 4;
   const int64_t total = E * NP * (int64_t)NSL * M * M;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
@@ -733,7 +801,7 @@ __global__ void fac_to_em64_kernel(LevelOrder ord, const void* __restrict__ in, 
     const int64_t gn = i / ((int64_t)M * M * NSL);
     const int64_t e = gn / NP;
     const int a = (int)(gn % NP);
-    out[i] = Store<PIN>::get(in, fac_index(e, ord.rank[a] * M + c, slot * M + cp, NR, NJP));
+    out[i] = Store<PIN>::get(in, fac_index(e, ord.rank[a] * M + c, row_pos_of(D, P, a, slot) * M + cp, NR, NJP));
   }
 }
 
@@ -809,7 +877,7 @@ hipError_t launch_precond_factor(const DevCtx& dc, const void* K11, const void* 
         hipLaunchKernelGGL((factor_kernel<D, P, EQ, PREC_F64>), dim3((unsigned)dc.E), dim3(64), 0, dc.stream, dc.E,
                            em);
         hipLaunchKernelGGL((em_to_fac_kernel<PREC_F64, PREC_F64>), dim3(copy_grid(nFac)), dim3(256), 0, dc.stream, dc.lev,
-                           em, Fem, dc.E, dc.NP, dc.M, nsl);
+                           em, Fem, dc.E, dc.NP, dc.M, nsl, dc.D, dc.P);
       } else {
         float* em = (float*)Fwork + nF;
         auto k = form_kernel<D, P, EQ, PR, PREC_F32>;
@@ -828,10 +896,10 @@ hipError_t launch_precond_factor(const DevCtx& dc, const void* K11, const void* 
         hipLaunchKernelGGL((factor_kernel<D, P, EQ, PREC_F32>), dim3((unsigned)dc.E), dim3(64), 0, dc.stream, dc.E, em);
         if (fprec == PREC_BF16)
           hipLaunchKernelGGL((em_to_fac_kernel<PREC_F32, PREC_BF16>), dim3(copy_grid(nFac)), dim3(256), 0, dc.stream,
-                             dc.lev, em, Fem, dc.E, dc.NP, dc.M, nsl);
+                             dc.lev, em, Fem, dc.E, dc.NP, dc.M, nsl, dc.D, dc.P);
         else
           hipLaunchKernelGGL((em_to_fac_kernel<PREC_F32, PREC_F32>), dim3(copy_grid(nFac)), dim3(256), 0, dc.stream,
-                             dc.lev, em, Fem, dc.E, dc.NP, dc.M, nsl);
+                             dc.lev, em, Fem, dc.E, dc.NP, dc.M, nsl, dc.D, dc.P);
       }
       return hipGetLastError();
     })
@@ -844,7 +912,7 @@ hipError_t launch_factors_to_f64(const DevCtx& dc, const void* Fem, int fprec, d
   const int64_t n = dc.E * dc.NP * (int64_t)(nsl * dc.M * dc.M);
   LDG_PREC_DISPATCH(fprec, {
     hipLaunchKernelGGL((fac_to_em64_kernel<PR>), dim3(copy_grid(n)), dim3(256), 0, dc.stream, dc.lev, Fem, out, dc.E,
-                       dc.NP, dc.M, nsl);
+                       dc.NP, dc.M, nsl, dc.D, dc.P);
     return hipGetLastError();
   })
 }

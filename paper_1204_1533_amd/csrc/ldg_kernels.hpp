@@ -37,6 +37,64 @@ __host__ __device__ constexpr int elems_per_block(int NP, int M) {
 // as [E][NJP / 4][NR][4]: a row's entries come in chunks of 4, and the same
 // chunk of consecutive rows is contiguous, so that one load per chunk by
 // consecutive rows reads one contiguous run.
+// Order of a factor row's blocks in the apply layout: the blocks left of the
+// diagonal (direction 0 positions 0 .. c_0 - 1, then direction 1, ..., each
+// ascending), the diagonal block, then the blocks right of it (same order).
+// A row of level L = c_0 + .. + c_{D-1} has exactly L blocks on the left, so
+// every row of a level has its lower part in positions 0 .. L-1.
+// row_slot_at: line slot (slot_col numbering) at position pos of node a's row;
+// row_pos_of: the inverse.
+__host__ __device__ inline int row_slot_at(int D, int P, int a, int pos) {
+  const int N1 = P + 1;
+  int cd[3] = {0, 0, 0}, L = 0;
+  for (int d = 0, r = a; d < D; ++d, r /= N1) {
+    cd[d] = r % N1;
+    L += cd[d];
+  }
+  if (pos == L) return cd[0];
+  if (pos < L) {
+    for (int n = 0; n < D; ++n) {
+      if (pos < cd[n]) return n == 0 ? pos : N1 + (n - 1) * P + pos;
+      pos -= cd[n];
+    }
+  }
+  int u = pos - L - 1;
+  for (int n = 0; n < D; ++n) {
+    const int cnt = P - cd[n];
+    if (u < cnt) {
+      const int t = cd[n] + 1 + u;
+      return n == 0 ? t : N1 + (n - 1) * P + (t - 1);
+    }
+    u -= cnt;
+  }
+  return -1;
+}
+__host__ __device__ inline int row_pos_of(int D, int P, int a, int slot) {
+  const int N1 = P + 1;
+  int cd[3] = {0, 0, 0}, L = 0;
+  for (int d = 0, r = a; d < D; ++d, r /= N1) {
+    cd[d] = r % N1;
+    L += cd[d];
+  }
+  int n, t;
+  if (slot < N1) {
+    n = 0;
+    t = slot;
+  } else {
+    n = 1 + (slot - N1) / P;
+    const int r = (slot - N1) % P;
+    t = r < cd[n] ? r : r + 1;
+  }
+  if (t == cd[n]) return L;
+  int before = 0;
+  if (t < cd[n]) {
+    for (int m = 0; m < n; ++m) before += cd[m];
+    return before + t;
+  }
+  for (int m = 0; m < n; ++m) before += P - cd[m];
+  return L + 1 + before + (t - cd[n] - 1);
+}
+
 __host__ __device__ constexpr int64_t fac_index(int64_t e, int r, int j, int NR, int NJP) {
   return ((e * (NJP / 4) + (j >> 2)) * NR + r) * 4 + (j & 3);
 }
