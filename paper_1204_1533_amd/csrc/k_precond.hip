@@ -159,8 +159,11 @@ struct FormLayout {
   static constexpr size_t bytes = sizeof(double) * ndoubles;
 };
 
-// Writes A~ (line slots, [slot][c][c'][E*Np]) in the working precision WP of the factorisation.
-template <int D, int P, int EQ, int PR, int WP>
+// Writes A~ (line slots) in the working precision WP of the factorisation,
+// node-fastest [slot][c][c'][E*Np] (EM = false) or element-major
+// [E*Np][slot][c][c'] (EM = true: each element's rows are written by one
+// workgroup, so the region is complete in the cache before it is written back).
+template <int D, int P, int EQ, int PR, int WP, bool EM>
 __global__ void __launch_bounds__(NT_ELEM) form_kernel(LineOps ops, MeshParams mp, const void* __restrict__ K11,
                                                        const void* __restrict__ K12, double alpha, double gamma,
                                                        void* __restrict__ F) {
@@ -336,7 +339,8 @@ __global__ void __launch_bounds__(NT_ELEM) form_kernel(LineOps ops, MeshParams m
 #pragma unroll
         for (int k = 0; k < M; ++k) {
           const double v = Store<PR>::get(K11, ((int64_t)(slot * M + c) * M + k) * NN + gn) + prod[k];
-          Store<WP>::put(F, ((int64_t)(slot * M + c) * M + k) * NN + gn, -gamma * v);
+          Store<WP>::put(F, EM ? (gn * NSL + slot) * (M * M) + c * M + k : ((int64_t)(slot * M + c) * M + k) * NN + gn,
+                         -gamma * v);
         }
       }
     }
@@ -351,7 +355,7 @@ __global__ void __launch_bounds__(NT_ELEM) form_kernel(LineOps ops, MeshParams m
       }
       v = -gamma * v;
       if (c == k) v += alpha;
-      Store<WP>::put(F, ((int64_t)(self * M + c) * M + k) * NN + gn, v);
+      Store<WP>::put(F, EM ? (gn * NSL + self) * (M * M) + c * M + k : ((int64_t)(self * M + c) * M + k) * NN + gn, v);
     }
   }
 }
@@ -425,11 +429,86 @@ __device__ __forceinline__ void invert_block(double A[M][M], double Inv[M][M]) {
     for (int j = 0; j < M; ++j) Inv[i][j] = W[i][M + j];
 }
 
-// One wavefront per element; lanes = (row of the current level, component row c).
+// Rows of the largest level of a (p+1)^D node grid: nodes with coordinate sum
+// floor(D p / 2), times the m components.
+template <int D, int P, int EQ>
+__host__ __device__ constexpr int max_level_rows() {
+  int best = 0;
+  for (int L = 0; L <= D * P; ++L) {
+    int cnt = 0;
+    for (int a = 0; a < ipow(P + 1, D); ++a) {
+      int s = 0, r = a;
+      for (int d = 0; d < D; ++d) {
+        s += r % (P + 1);
+        r /= (P + 1);
+      }
+      cnt += s == L;
+    }
+    best = cnt > best ? cnt : best;
+  }
+  return best * Eq<D, EQ>::M;
+}
+// x = A^{-1} e_col by Gaussian elimination with partial pivoting (row swaps
+// with compile-time indices, as in invert_block).
+template <int M>
+__device__ __forceinline__ void solve_unit_column(double A[M][M], int col, double x[M]) {
+  double b[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) b[i] = i == col ? 1.0 : 0.0;
+#pragma unroll
+  for (int c = 0; c < M; ++c) {
+    int piv = c;
+    double best = fabs(A[c][c]);
+#pragma unroll
+    for (int r = c + 1; r < M; ++r)
+      if (fabs(A[r][c]) > best) {
+        best = fabs(A[r][c]);
+        piv = r;
+      }
+#pragma unroll
+    for (int r = c + 1; r < M; ++r)
+      if (r == piv) {
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+          const double t = A[c][j];
+          A[c][j] = A[r][j];
+          A[r][j] = t;
+        }
+        const double t = b[c];
+        b[c] = b[r];
+        b[r] = t;
+      }
+#pragma unroll
+    for (int r = c + 1; r < M; ++r) {
+      const double f = A[r][c] / A[c][c];
+#pragma unroll
+      for (int j = c; j < M; ++j) A[r][j] -= f * A[c][j];
+      b[r] -= f * b[c];
+    }
+  }
+#pragma unroll
+  for (int i = M - 1; i >= 0; --i) {
+    double s = b[i];
+#pragma unroll
+    for (int j = i + 1; j < M; ++j) s -= A[i][j] * x[j];
+    x[i] = s / A[i][i];
+  }
+}
+
+// Work items per element of the factorisation: enough for the largest level's
+// rows in one pass (up to 256).
+template <int D, int P, int EQ>
+__host__ __device__ constexpr int factor_threads() {
+  constexpr int r = max_level_rows<D, P, EQ>();
+  return r <= 64 ? 64 : (r <= 128 ? 128 : 256);
+}
+
+// One workgroup per element; work items = (row of the current level, component row c).
 template <int D, int P, int EQ, int WP>
-__global__ void __launch_bounds__(64) factor_kernel(int64_t E, void* __restrict__ F) {
+__global__ void __launch_bounds__((factor_threads<D, P, EQ>())) factor_kernel(int64_t E, void* __restrict__ F) {
   constexpr int N1 = P + 1, NP = ipow(N1, D), M = Eq<D, EQ>::M;
-  constexpr int RPP = 64 / M;  // rows per pass
+  constexpr int NT = factor_threads<D, P, EQ>();
+  constexpr int RPP = NT / M;  // rows per pass
   constexpr int NSLMM = (D * P + 1) * M * M;
   // F: element-major [E Np][slot][c][c'], so one workgroup's rows are one
   // contiguous block
@@ -487,19 +566,25 @@ __global__ void __launch_bounds__(64) factor_kernel(int64_t E, void* __restrict_
         }
       }
       __syncthreads();
-      if (active && c == 0) {
+      // inverse of the U diagonal block: work item c of the row takes column c
+      // (A x = e_c by elimination with partial pivoting), all M in parallel
+      double xcol[M];
+      if (active) {
         const int64_t gi = e * NP + i;
         const int self_i = i % N1;
-        double A[M][M], Inv[M][M];
+        double A[M][M];
 #pragma unroll
         for (int a = 0; a < M; ++a)
 #pragma unroll
           for (int b = 0; b < M; ++b) A[a][b] = Store<WP>::get(F, gi * NSLMM + (self_i * M + a) * M + b);
-        invert_block<M>(A, Inv);
+        solve_unit_column<M>(A, c, xcol);
+      }
+      __syncthreads();  // every column read the block before any is overwritten
+      if (active) {
+        const int64_t gi = e * NP + i;
+        const int self_i = i % N1;
 #pragma unroll
-        for (int a = 0; a < M; ++a)
-#pragma unroll
-          for (int b = 0; b < M; ++b) Store<WP>::put(F, gi * NSLMM + (self_i * M + a) * M + b, Inv[a][b]);
+        for (int a = 0; a < M; ++a) Store<WP>::put(F, gi * NSLMM + (self_i * M + a) * M + c, xcol[a]);
       }
       __syncthreads();
     }
@@ -559,25 +644,6 @@ __device__ __forceinline__ int node_level(int a) {
   return s;
 }
 
-// Rows of the largest level of a (p+1)^D node grid: nodes with coordinate sum
-// floor(D p / 2), times the m components.
-template <int D, int P, int EQ>
-__host__ __device__ constexpr int max_level_rows() {
-  int best = 0;
-  for (int L = 0; L <= D * P; ++L) {
-    int cnt = 0;
-    for (int a = 0; a < ipow(P + 1, D); ++a) {
-      int s = 0, r = a;
-      for (int d = 0; d < D; ++d) {
-        s += r % (P + 1);
-        r /= (P + 1);
-      }
-      cnt += s == L;
-    }
-    best = cnt > best ? cnt : best;
-  }
-  return best * Eq<D, EQ>::M;
-}
 template <int D, int P, int EQ>
 struct ApplyShape {
   static constexpr int TPE = max_level_rows<D, P, EQ>();  // work items per element: one level's rows
@@ -764,27 +830,41 @@ __global__ void __launch_bounds__((ApplyShape<D, P, EQ>::NT)) apply_kernel(Level
     for (int i = lane; i < NR; i += TPE) z[e * NR + i] = y[(i % NP) * YS + i / NP];
 }
 
-// element-major factors [E Np][slot][c][c'] -> apply layout (zero padding)
+// element-major factors [E Np][slot][c][c'] -> apply layout (zero padding):
+// one work item per 4-entry chunk of a row, written with one 8- to 32-byte
+// store; the slot at each row position comes from a table in LDS.
+constexpr int FAC_TABLE_MAX = NPMAX * 13;  // Np (Dp + 1) for p <= 4
 template <int PIN, int POUT>
-__global__ void em_to_fac_kernel(LevelOrder ord, const void* __restrict__ in, void* __restrict__ out, int64_t E,
-                                 int NP, int M, int NSL, int D, int P) {
+__global__ void __launch_bounds__(256) em_to_fac_kernel(LevelOrder ord, const void* __restrict__ in,
+                                                        void* __restrict__ out, int64_t E, int NP, int M, int NSL,
+                                                        int D, int P) {
+  using T = typename Store<POUT>::type;
+  struct alignas(4 * sizeof(T)) T4 {
+    T x[4];
+  };
+  __shared__ int8_t slot_at[FAC_TABLE_MAX];
+  for (int i = threadIdx.x; i < NP * NSL; i += blockDim.x) slot_at[i] = (int8_t)row_slot_at(D, P, i / NSL, i % NSL);
+  __syncthreads();
   const int NR = NP * M, NJ = NSL * M, NJP = (NJ + 3) / 4 * 4;
-  const int64_t total = E * (int64_t)NJP * NR;
+  const int64_t total = E * (int64_t)(NJP / 4) * NR;  // chunks
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-    const int jj = (int)(i & 3);
-    const int64_t q = i >> 2;
-    const int rr = (int)(q % NR);
-    const int64_t q2 = q / NR;
+    const int rr = (int)(i % NR);
+    const int64_t q2 = i / NR;
     const int ch = (int)(q2 % (NJP / 4));
     const int64_t e = q2 / (NJP / 4);
-    const int j = ch * 4 + jj;
-    double v = 0.0;
-    if (j < NJ) {
-      const int a = ord.node[rr / M], c = rr % M, cp = j % M;
-      const int slot = row_slot_at(D, P, a, j / M);
-      v = Store<PIN>::get(in, ((e * NP + a) * NSL + slot) * (int64_t)(M * M) + c * M + cp);
+    const int a = ord.node[rr / M], c = rr % M;
+    T4 w;
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      const int j = ch * 4 + jj;
+      double x = 0.0;
+      if (j < NJ) {
+        const int slot = slot_at[a * NSL + j / M];
+        x = Store<PIN>::get(in, ((e * NP + a) * NSL + slot) * (int64_t)(M * M) + c * M + j % M);
+      }
+      Store<POUT>::put(w.x, jj, x);
     }
-    Store<POUT>::put(out, i, v);
+    reinterpret_cast<T4*>(out)[i] = w;
   }
 }
 
@@ -839,9 +919,9 @@ static unsigned copy_grid(int64_t n) {
   return (unsigned)(g > 65536 ? 65536 : g);
 }
 
-// A~ is formed node-fastest in Fwork, copied (At_copy, optional) in FP32,
-// transposed to the element-major layout in the second half of Fwork and
-// factorised there in place (FP64 arithmetic for FP64 factors, FP32
+// A~ is formed element-major in the second half of Fwork (or, when the
+// learned correction needs an FP32 node-fastest copy in At_copy, formed
+// node-fastest in Fwork, copied and transposed there) and factorised in place (FP64 arithmetic for FP64 factors, FP32
 // otherwise), then rearranged into the apply layout in Fem in storage
 // precision fprec.  With dense != null the element-major A~ is instead
 // expanded and factorised exactly (dense [E][NR][NR] LU in FP64).
@@ -861,44 +941,48 @@ hipError_t launch_precond_factor(const DevCtx& dc, const void* K11, const void* 
     LDG_PREC_DISPATCH(prec, {
       if (fprec == PREC_F64) {
         double* em = (double*)Fwork + nF;
-        auto k = form_kernel<D, P, EQ, PR, PREC_F64>;
+        auto k = At_copy ? form_kernel<D, P, EQ, PR, PREC_F64, false> : form_kernel<D, P, EQ, PR, PREC_F64, true>;
         if (bytes > 65536) {
           const hipError_t err =
               hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
           if (err != hipSuccess) return err;
         }
         hipLaunchKernelGGL(k, dim3((unsigned)dc.E), dim3(NT_ELEM), bytes, dc.stream, dc.ops, dc.mp, K11, K12, alpha,
-                           gamma, Fwork);
-        if (At_copy)
+                           gamma, At_copy ? Fwork : (void*)em);
+        if (At_copy) {
           hipLaunchKernelGGL((convert_kernel<PREC_F64, PREC_F32>), dim3(copy_grid(nF)), dim3(256), 0, dc.stream, Fwork,
                              At_copy, nF);
-        hipLaunchKernelGGL((relayout_kernel<PREC_F64>), tgrid, dim3(256), 0, dc.stream, Fwork, em, NN, nq);
+          hipLaunchKernelGGL((relayout_kernel<PREC_F64>), tgrid, dim3(256), 0, dc.stream, Fwork, em, NN, nq);
+        }
         if (dense) return launch_blocklu_factor(dc, em, PREC_F64, dense);
-        hipLaunchKernelGGL((factor_kernel<D, P, EQ, PREC_F64>), dim3((unsigned)dc.E), dim3(64), 0, dc.stream, dc.E,
+        hipLaunchKernelGGL((factor_kernel<D, P, EQ, PREC_F64>), dim3((unsigned)dc.E), dim3(factor_threads<D, P, EQ>()), 0,
+                           dc.stream, dc.E,
                            em);
-        hipLaunchKernelGGL((em_to_fac_kernel<PREC_F64, PREC_F64>), dim3(copy_grid(nFac)), dim3(256), 0, dc.stream, dc.lev,
+        hipLaunchKernelGGL((em_to_fac_kernel<PREC_F64, PREC_F64>), dim3(copy_grid(nFac / 4)), dim3(256), 0, dc.stream, dc.lev,
                            em, Fem, dc.E, dc.NP, dc.M, nsl, dc.D, dc.P);
       } else {
         float* em = (float*)Fwork + nF;
-        auto k = form_kernel<D, P, EQ, PR, PREC_F32>;
+        auto k = At_copy ? form_kernel<D, P, EQ, PR, PREC_F32, false> : form_kernel<D, P, EQ, PR, PREC_F32, true>;
         if (bytes > 65536) {
           const hipError_t err =
               hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
           if (err != hipSuccess) return err;
         }
         hipLaunchKernelGGL(k, dim3((unsigned)dc.E), dim3(NT_ELEM), bytes, dc.stream, dc.ops, dc.mp, K11, K12, alpha,
-                           gamma, Fwork);
-        if (At_copy)
+                           gamma, At_copy ? Fwork : (void*)em);
+        if (At_copy) {
           hipLaunchKernelGGL((convert_kernel<PREC_F32, PREC_F32>), dim3(copy_grid(nF)), dim3(256), 0, dc.stream, Fwork,
                              At_copy, nF);
-        hipLaunchKernelGGL((relayout_kernel<PREC_F32>), tgrid, dim3(256), 0, dc.stream, Fwork, em, NN, nq);
+          hipLaunchKernelGGL((relayout_kernel<PREC_F32>), tgrid, dim3(256), 0, dc.stream, Fwork, em, NN, nq);
+        }
         if (dense) return launch_blocklu_factor(dc, em, PREC_F32, dense);
-        hipLaunchKernelGGL((factor_kernel<D, P, EQ, PREC_F32>), dim3((unsigned)dc.E), dim3(64), 0, dc.stream, dc.E, em);
+        hipLaunchKernelGGL((factor_kernel<D, P, EQ, PREC_F32>), dim3((unsigned)dc.E), dim3(factor_threads<D, P, EQ>()), 0,
+                           dc.stream, dc.E, em);
         if (fprec == PREC_BF16)
-          hipLaunchKernelGGL((em_to_fac_kernel<PREC_F32, PREC_BF16>), dim3(copy_grid(nFac)), dim3(256), 0, dc.stream,
+          hipLaunchKernelGGL((em_to_fac_kernel<PREC_F32, PREC_BF16>), dim3(copy_grid(nFac / 4)), dim3(256), 0, dc.stream,
                              dc.lev, em, Fem, dc.E, dc.NP, dc.M, nsl, dc.D, dc.P);
         else
-          hipLaunchKernelGGL((em_to_fac_kernel<PREC_F32, PREC_F32>), dim3(copy_grid(nFac)), dim3(256), 0, dc.stream,
+          hipLaunchKernelGGL((em_to_fac_kernel<PREC_F32, PREC_F32>), dim3(copy_grid(nFac / 4)), dim3(256), 0, dc.stream,
                              dc.lev, em, Fem, dc.E, dc.NP, dc.M, nsl, dc.D, dc.P);
       }
       return hipGetLastError();
