@@ -37,30 +37,34 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=256, help="elements timed on the CPU oracle")
     ap.add_argument("--no-rk4", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the 16^3, DIRK3 and 512^2 measurements")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="copy 1 GiB between two device buffers first (a reference kernel for profiler counters)")
     return ap.parse_args()
 
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "jacvec_tgv32p4_bf16_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "solver_kernels_tgv32p4_bf16_traffic.md")
+TRAFFIC_SOURCE = {"jacvec": "k_precond.hip", "precond_apply": "k_precond.hip", "k21_product": "k_k21.hip"}
 
 
-def measured_traffic():
-    """HBM bytes per launch of the split product from the committed rocprofv3 counter summary.
+def measured_traffic(kernel):
+    """HBM bytes per launch of one solver kernel from the committed rocprofv3 counter summary.
 
-    The summary records FETCH_SIZE / WRITE_SIZE per dispatch scaled by the same counters on a
-    plain conversion kernel of known size, and the SHA-256 of the kernel source it was taken
-    with; a changed source makes the figure stale, and then None is reported.
+    The summary records FETCH_SIZE / WRITE_SIZE per dispatch, each scaled by what the same counter
+    reads for a plain copy kernel of known size, and the SHA-256 of the kernel's source file it was
+    taken with; a changed source makes the figure stale, and then None is reported.
     """
     import hashlib
     import re
-    if not os.path.exists(TRAFFIC_FILE):
+    if not os.path.exists(TRAFFIC_FILE) or kernel not in TRAFFIC_SOURCE:
         return None
     txt = open(TRAFFIC_FILE).read()
-    m_b = re.search(r"jacvec_traffic_bytes_per_launch\s*=\s*([0-9.eE+]+)", txt)
-    m_h = re.search(r"source_sha256\s*=\s*([0-9a-f]{64})", txt)
+    m_b = re.search(r"traffic_bytes_per_launch\[" + kernel + r"\]\s*=\s*([0-9.eE+]+)", txt)
+    fname = TRAFFIC_SOURCE[kernel]
+    m_h = re.search(r"source_sha256\[" + re.escape(fname) + r"\]\s*=\s*([0-9a-f]{64})", txt)
     if not m_b or not m_h:
         return None
-    src = os.path.join(ROOT, "paper_1204_1533_amd", "csrc", "k_precond.hip")
+    src = os.path.join(ROOT, "paper_1204_1533_amd", "csrc", fname)
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != m_h.group(1):
         return None
     return float(m_b.group(1))
@@ -99,8 +103,9 @@ def roofline(pr, reps, prec):
                    "traffic": None, "avg_ms": avg_ms, "launches": n, "bytes_per_launch": byts,
                    "share_of_step_ms": tot / len(reps)}
     dom = max(allk, key=lambda k: allk[k]["share_of_step_ms"]) if allk else None
-    if "jacvec" in allk and prec == 2 and me.n_elem == 32768 and p == 4:
-        allk["jacvec"]["traffic"] = measured_traffic()
+    if prec == 2 and me.n_elem == 32768 and p == 4:
+        for k in allk:
+            allk[k]["traffic"] = measured_traffic(k)
     d = dict(allk[dom]) if dom else None
     if d:
         d["kernel"] = dom
@@ -375,6 +380,12 @@ def main():
     from paper_1204_1533_amd import Context, LDG_BF16, LDG_F64, LDG_F32
 
     torch.cuda.set_device(0)
+    if args.calib_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     pr = configs.config4() if args.config == "C4" else configs.config3()
     chosen_prec = LDG_BF16 if args.config == "C4" else LDG_F32
     log(f"[bench] workload {pr.name}: E={pr.mesh.n_elem} p={pr.mesh.p} dofs={pr.n_dof}")
