@@ -21,7 +21,12 @@ What is computed, and where the paper defines it:
   Fhat = F(u_in, q_in).n + C11_D |n| (u_in - g_D), uhat = g_D (eqs.
   dirichlet1/2); inviscid Dirichlet faces take Roe(g_D, u_in) (the
   characteristic far-field condition);
-* Neumann faces (eqs. neumann1/2 with C22 = 0): Fhat . n = |n| g_N, uhat = u_in;
+* Neumann faces (eqs. neumann1/2): Fhat . n = |n| g_N, uhat = u_in - C22 (F(u_in, q_in) . nbar - g_N);
+* C22 (eqs. ldgflux1/2): uhat gains C22 [[F . nbar]] = C22 (F(u_out, q_out) - F(u_in, q_in)) . nbar
+  on interior faces (nbar the unit outward normal), so the auxiliary equation
+  couples q across faces: the coupled system of Section 4.1 with unknowns
+  (U, Q), residuals R(U, Q) and Q - G(U, Q); C22 = 0 (the default) gives the
+  reduced system where Q = D(U) is eliminated element by element;
 * slip walls: Roe(u_m, u_in) with the mirror state u_m (normal momentum
   reflected), no viscous flux through the wall, uhat = u_in;
   boundary kinds come from face_nbr = -(kind + 1): 0 Dirichlet, 1 Neumann,
@@ -50,6 +55,8 @@ DT = torch.float64
 
 
 def _t(x):
+    if isinstance(x, torch.Tensor):
+        return x.to(DT)
     return torch.as_tensor(np.asarray(x), dtype=DT)
 
 
@@ -57,7 +64,7 @@ class LineDG:
     """The discrete operator for one mesh and one equation set."""
 
     def __init__(self, dim, p, xyz, face_nbr, nbr_node, switch_plus, physics: Physics,
-                 c11_interior=0.0, c11_dirichlet=10.0, source=None, gD=None, nodes="gll", gN=None):
+                 c11_interior=0.0, c11_dirichlet=10.0, source=None, gD=None, nodes="gll", gN=None, c22=0.0):
         self.D = dim
         self.p = p
         self.n1 = p + 1
@@ -82,6 +89,7 @@ class LineDG:
         self.source = None if source is None else _t(source)
         self.gD = None if gD is None else _t(gD)
         self.gN = None if gN is None else _t(gN)
+        self.c22 = float(c22)
         self.nslot_line = dim * p + 1
         self.nslot11 = self.nslot_line + 2 * dim
         self.nslot12 = self.nslot_line + dim
@@ -213,12 +221,19 @@ class LineDG:
         sel = torch.where((kind > 0)[..., None], u_in, sel)
         return torch.where((kind == 0)[..., None], gD, sel)
 
-    def gradient(self, U, elems=None, homogeneous=False, geo=None):
-        """Q = D(U) for the given elements: [Ne, m, D, Np] (eqs. semidisc2-2)."""
+    def gradient(self, U, elems=None, homogeneous=False, geo=None, Q=None):
+        """Q = D(U) for the given elements: [Ne, m, D, Np] (eqs. semidisc2-2).
+
+        With C22 != 0 the trace uhat involves the normal viscous flux of both
+        sides, so the gradient field ``Q`` [E, m, D, Np] entering it must be
+        given: the result is then G(U, Q) of the coupled system.
+        """
         if elems is None:
             elems = torch.arange(self.E)
         elems = torch.as_tensor(elems, dtype=torch.int64)
         U = _t(U)
+        if self.c22 != 0.0 and Q is None:
+            raise ValueError("C22 != 0: the gradient needs the current Q")
         if geo is None:
             geo = self.geometry(elems)
         Ne = len(elems)
@@ -226,6 +241,10 @@ class LineDG:
         for n in range(self.D):
             ul = self.to_lines(U[elems], n)  # [Ne, NL, N1, m]
             Sp = self.switch_plus[elems, n][:, None].expand(Ne, self.NL)
+            if self.c22 != 0.0:
+                Qa = _t(Q)
+                ql = self.to_lines(Qa[elems].reshape(Ne, self.m * self.D, self.Np), n).reshape(
+                    Ne, self.NL, self.n1, self.m, self.D)
             uh = []
             for s in (0, 1):
                 uo, bnd = self._outside(U, elems, n, s)
@@ -233,7 +252,22 @@ class LineDG:
                 S = Sp if s == 1 else -Sp
                 uin = ul[:, :, self.p if s == 1 else 0]
                 kind = self._kind(elems, n, s)[:, None].expand(Ne, self.NL)
-                uh.append(self._uhat(uin, uo, S, kind, gD))
+                u_hat = self._uhat(uin, uo, S, kind, gD)
+                if self.c22 != 0.0:
+                    # C22 [[F . nbar]]: interior faces take the jump of the normal viscous flux,
+                    # Neumann faces its difference from g_N; Dirichlet faces and slip walls none
+                    nrm = geo["n1"][n] if s == 1 else geo["n0"][n]  # outward, [Ne, NL, D]
+                    nbar = nrm / torch.sqrt((nrm * nrm).sum(-1, keepdim=True))
+                    qin = ql[:, :, self.p if s == 1 else 0]
+                    qo = self._outside(Qa.reshape(self.E, self.m * self.D, self.Np), elems, n, s)[0].reshape(
+                        Ne, self.NL, self.m, self.D)
+                    Fin = (self.ph.flux_vis(uin, qin) * nbar[..., None, :]).sum(-1)
+                    Fout = (self.ph.flux_vis(uo, qo) * nbar[..., None, :]).sum(-1)
+                    gN = torch.zeros_like(uo) if homogeneous else self._gN_face(elems, n, s)
+                    jump = torch.where((kind == 1)[..., None], Fin - gN, Fin - Fout)
+                    jump = torch.where(((kind == 0) | (kind == 2))[..., None], torch.zeros_like(jump), jump)
+                    u_hat = u_hat + self.c22 * jump
+                uh.append(u_hat)
             b = self.grad_line_rhs(ul, uh[0], uh[1], geo["ag"][n], geo["n0"][n], geo["n1"][n])
             d = self._mass_solve(b)  # [Ne, NL, N1, m, D]
             acc += self.from_lines(d.reshape(Ne, self.NL, self.n1, self.m * self.D), n).reshape(
@@ -318,14 +352,21 @@ class LineDG:
         qidx[allel] = torch.arange(len(allel))
         return allel, qidx
 
-    def residual(self, U, elems=None, return_abs=False):
-        """R = -(1/J) sum_n r^(n) + S for the given elements: [Ne, m, Np]."""
+    def residual(self, U, elems=None, return_abs=False, Q=None):
+        """R = -(1/J) sum_n r^(n) + S for the given elements: [Ne, m, Np].
+
+        ``Q`` [E, m, D, Np], when given, is used as the gradient (the coupled system's
+        unknown); otherwise Q = D(U) (the reduced system, C22 = 0)."""
         if elems is None:
             elems = torch.arange(self.E)
         elems = torch.as_tensor(elems, dtype=torch.int64)
         U = _t(U)
         allel, qidx = self._with_neighbours(elems)
-        if self.ph.has_viscous:
+        if Q is not None:
+            Q = _t(Q)[allel]
+        elif self.ph.has_viscous:
+            if self.c22 != 0.0:
+                raise ValueError("C22 != 0: Q is an unknown of the coupled system and must be given")
             Q = self.gradient(U, allel)
         else:
             Q = torch.zeros(len(allel), self.m, self.D, self.Np, dtype=DT)

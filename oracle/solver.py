@@ -19,6 +19,9 @@ TEST INFRASTRUCTURE ONLY: part of the plain FP64 CPU oracle.
   modified Gram-Schmidt, Givens rotations; stop when ||b - A x|| <= rtol ||b||.
 * Classical four-stage Runge-Kutta and the three-stage DIRK with Newton
   stage solves (Section 4.1).
+* The coupled (U, Q) system of Section 4.1 (needed when C22 != 0): for a
+  linear problem its matrix, formed by forward differentiation, and a dense
+  solve.
 """
 from __future__ import annotations
 
@@ -26,6 +29,7 @@ import math
 
 import numpy as np
 import torch
+from torch.func import jacfwd
 
 from .linedg import LineDG, DT
 
@@ -343,6 +347,34 @@ def sparse_blocks(d: LineDG, K11, K12, K21):
                     lambda Kn, s, i, j: Kn[:, :, s, i % D] * (1.0 if i // D == j else 0.0))
     S21 = sp.csr_matrix((v, (r, c)), shape=(nq, n))
     return S11, S12, S21
+
+
+def coupled_residuals(d: LineDG, U, Q):
+    """The coupled system of Section 4.1 with Q an unknown: (R(U, Q), Q - G(U, Q))."""
+    return d.residual(U, Q=Q), Q - d.gradient(U, Q=Q)
+
+
+def coupled_steady_solve(d: LineDG):
+    """Steady solve of the coupled (U, Q) system for a linear problem (Poisson), any C22.
+
+    F(U, Q) = [-R(U, Q); Q - G(U, Q)] is affine in (U, Q); its matrix is formed by forward
+    differentiation of F at zero (one column per unknown) and the system F = 0 is solved by a
+    dense LU.  Returns (U [E, m, Np], Q [E, m, D, Np]).
+    """
+    E, m, D, Np = d.E, d.m, d.D, d.Np
+    nu, nq = E * m * Np, E * m * D * Np
+
+    def F(x):
+        U = x[:nu].reshape(E, m, Np)
+        Q = x[nu:].reshape(E, m, D, Np)
+        R, RQ = coupled_residuals(d, U, Q)
+        return torch.cat([-R.reshape(-1), RQ.reshape(-1)])
+
+    x0 = torch.zeros(nu + nq, dtype=DT)
+    F0 = F(x0)
+    A = jacfwd(F)(x0)
+    x = torch.linalg.solve(A, -F0)
+    return x[:nu].reshape(E, m, Np), x[nu:].reshape(E, m, D, Np)
 
 
 def steady_direct_solve(d: LineDG, U0=None):
