@@ -189,6 +189,41 @@ ldg_status ldg_precond_apply(ldg_ctx ctx, const double* r_dev, double* z_dev);
  * Errors: LDG_E_INVALID (kind), LDG_E_UNSUPPORTED (block LU with Np m > 768). */
 ldg_status ldg_set_preconditioner(ldg_ctx ctx, int32_t kind);
 
+/* Section 4.1, eqs. ldgflux1/ldgflux2 and neumann1/neumann2: the coefficient
+ * C22 >= 0 of the jump of the normal viscous flux in the trace of u, used by
+ * ldg_coupled_solve (Poisson only).  On an interior face the trace gains
+ * C22 (F(q_in) - F(q_out)) . nhat_in with nhat_in the unit normal out of the
+ * element whose equation is being formed; on a Neumann face
+ * C22 (F(q_in) . nhat - g_N); none on Dirichlet faces.  The reduced scheme of
+ * ldg_gradient / ldg_residual / ldg_newton_step (C22 = 0) is unaffected.
+ * Errors: LDG_E_INVALID (negative or non-finite), LDG_E_UNSUPPORTED (C22 != 0
+ * for an equation other than Poisson). */
+ldg_status ldg_set_c22(ldg_ctx ctx, double c22);
+
+/* Section 4.1: steady solution of the linear problem in the coupled unknowns
+ * (U, Q), F(U, Q) = [-R(U, Q); Q - G(U, Q)] = 0 with G the gradient whose
+ * trace carries the C22 term of ldg_set_c22, by flexible GMRES(restart) from
+ * zero in FP64 (the paper uses a sparse direct solver here).  Preconditioner:
+ * an approximate inverse of the C22 = 0 Jacobian [[-K11, -K12], [-K21, I]] --
+ * U from an inner GMRES(restart) solve of the reduced system
+ * -(K11 + K12 K21) U = r_U + K12 r_Q to inner_rtol (at most restart
+ * iterations, with the element-block preconditioner of the kind set by
+ * ldg_set_preconditioner), then Q = r_Q + K21 U.  Assembles K11, K12 and the
+ * preconditioner with alpha = 0, gamma = 1 in FP64 (replacing any previous
+ * assembly).  U_dev [E][m][Np] and Q_dev [E][m][D][Np] (out).  Stops when
+ * ||b - A x|| <= rtol ||b|| (the true residual) or after max_iters outer
+ * iterations; iters_out, inner_iters_out (total inner iterations) and
+ * relres_out (any may be NULL) report them.  Work memory
+ * ((2 restart + 6)(ndof + nq) + ndof doubles, and the reduced system's Krylov
+ * space) is allocated by the first call.  Synchronises the stream.
+ * Errors: LDG_E_INVALID (rtol <= 0, inner_rtol outside (0, 1), restart outside
+ * 1..120, max_iters < 1, null or aliased U/Q), LDG_E_UNSUPPORTED (not
+ * Poisson), LDG_E_NOT_CONVERGED (U, Q then hold the last iterate),
+ * LDG_E_NONFINITE. */
+ldg_status ldg_coupled_solve(ldg_ctx ctx, double* U_dev, double* Q_dev, double rtol, double inner_rtol,
+                             int32_t restart, int32_t max_iters, int32_t* iters_out, int32_t* inner_iters_out,
+                             double* relres_out);
+
 /* Copy the assembled operators out in FP64, line-block layout:
  * K11_dev [E][Np][Dp+1+2D][m][m], K12_dev [E][Np][Dp+1+D][m][m*D] (columns
  * (c', d) like Q), F_dev [E][Np][Dp+1][m][m] the BILU(0) factors (strictly

@@ -299,7 +299,8 @@ struct GradLayout {
 
 template <int D, int P, int EQ>
 __global__ void __launch_bounds__(NT_ELEM) grad_kernel(LineOps ops, MeshParams mp, const double* __restrict__ U,
-                                                       double* __restrict__ Q, int homogeneous) {
+                                                       double* __restrict__ Q, int homogeneous,
+                                                       const double* __restrict__ Qc) {
   using L = GradLayout<D, P, EQ>;
   constexpr int N1 = L::N1, NG = L::NG, NP = L::NP, NL = L::NL, M = L::M, EPB = L::EPB;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -376,6 +377,42 @@ __global__ void __launch_bounds__(NT_ELEM) grad_kernel(LineOps ops, MeshParams m
 #pragma unroll
         for (int c = 0; c < M; ++c) sUh[i * M + c] = U[(nb * M + c) * NP + nd];
       }
+      if constexpr (Eq<D, EQ>::VIS) {
+        if (Qc && (kind == BC_INTERIOR || kind == BC_NEUMANN)) {
+          // C22 [[F . nbar]] with the inside as the positive side: interior faces
+          // (F_in - F_out) . nbar, Neumann faces F_in . nbar - g_N (nbar the unit outward normal)
+          double nbar[D], nn = 0.0;
+#pragma unroll
+          for (int d = 0; d < D; ++d) nn += sNh[i * D + d] * sNh[i * D + d];
+          nn = 1.0 / sqrt(nn);
+#pragma unroll
+          for (int d = 0; d < D; ++d) nbar[d] = sNh[i * D + d] * nn;
+          double uin[M], qin[M * D], Fin[M], Fout[M];
+#pragma unroll
+          for (int c = 0; c < M; ++c) {
+            uin[c] = sU[(e * M + c) * NP + nin];
+            Fin[c] = 0.0;
+            Fout[c] = 0.0;
+          }
+#pragma unroll
+          for (int k = 0; k < M * D; ++k) qin[k] = Qc[(eg * M * D + k) * NP + nin];
+          visc_flux_dot_add<D, EQ, double>(uin, qin, nbar, mp.gamma, mp.mu, mp.prandtl, Fin);
+          if (kind == BC_INTERIOR) {
+            const int nd = mp.nbr_node[(eg * 2 * D + f) * NL + l];
+            double uout[M], qout[M * D];
+#pragma unroll
+            for (int c = 0; c < M; ++c) uout[c] = U[(nb * M + c) * NP + nd];
+#pragma unroll
+            for (int k = 0; k < M * D; ++k) qout[k] = Qc[(nb * M * D + k) * NP + nd];
+            visc_flux_dot_add<D, EQ, double>(uout, qout, nbar, mp.gamma, mp.mu, mp.prandtl, Fout);
+          } else if (!homogeneous && mp.gN) {
+#pragma unroll
+            for (int c = 0; c < M; ++c) Fout[c] = mp.gN[((eg * 2 * D + f) * M + c) * NL + l];
+          }
+#pragma unroll
+          for (int c = 0; c < M; ++c) sUh[i * M + c] += mp.c22 * (Fin[c] - Fout[c]);
+        }
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -438,7 +475,7 @@ hipError_t launch_residual_tangent(const DevCtx& dc, const double* U, const doub
   })
 }
 
-hipError_t launch_gradient(const DevCtx& dc, const double* U, double* Q, bool homogeneous) {
+hipError_t launch_gradient(const DevCtx& dc, const double* U, double* Q, bool homogeneous, const double* Qc) {
   LDG_DISPATCH(dc, {
     using L = GradLayout<D, P, EQ>;
     static_assert(L::bytes <= LDS_PER_CU, "gradient workspace must fit one CU's LDS");
@@ -449,7 +486,7 @@ hipError_t launch_gradient(const DevCtx& dc, const double* U, double* Q, bool ho
     }
     const int64_t grid = (dc.E + L::EPB - 1) / L::EPB;
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT_ELEM), L::bytes, dc.stream, dc.ops, dc.mp, U, Q,
-                       homogeneous ? 1 : 0);
+                       homogeneous ? 1 : 0, dc.mp.c22 != 0.0 ? Qc : nullptr);
     return hipGetLastError();
   })
 }

@@ -28,6 +28,8 @@ struct ldg_ctx_s {
   int precond_kind = 0;       // ldg_precond_kind: 0 BILU(0), 1 exact element-block LU
   double* d_Dense = nullptr;  // [E][NR][NR] dense L\U of A~ (block LU)
   size_t capDense = 0;
+  double* d_cwork = nullptr;  // coupled (U, Q) solve: Krylov space and vectors
+  size_t cap_cwork = 0;
   double* d_geo = nullptr;    // per-element geometry record of the Jacobian assembly
   double* d_Jwork = nullptr;  // point flux Jacobians of the assembly
   size_t capJwork = 0;

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -82,7 +83,7 @@ void ldg_destroy(ldg_ctx c) {
   void* ptrs[] = {c->d_xyz, c->d_face_nbr, c->d_nbr_node, c->d_sw, c->d_gD, c->d_gN, c->d_S, c->d_Q, c->d_W, c->d_W2,
                   c->d_K11, c->d_K12, c->d_F, c->d_Fem, c->d_Ua, c->d_Qa, c->d_V, c->d_Z, c->d_R, c->d_G, c->d_x, c->d_r, c->d_z,
                   c->d_tmp, c->d_Un, c->d_partial, c->d_h, c->d_Uold, c->d_st_Un, c->d_st_comb, c->d_st_K,
-                  c->d_K21w, c->d_Dense, c->d_geo, c->d_Jwork};
+                  c->d_K21w, c->d_Dense, c->d_geo, c->d_Jwork, c->d_cwork};
   for (void* p : ptrs)
     if (p) hipFree(p);
   learned_free(c);
@@ -215,6 +216,7 @@ ldg_status ldg_create(const ldg_problem_desc* d, void* stream, ldg_ctx* out) {
   mp.gD = nullptr;
   mp.gN = nullptr;
   mp.S = nullptr;
+  mp.c22 = 0.0;
   *out = c;
   return LDG_OK;
 }
@@ -339,6 +341,15 @@ ldg_status ldg_jacobian_assemble(ldg_ctx c, const double* U, double alpha, doubl
   return assemble(c, U, alpha, gamma, prec, nullptr);
 }
 
+ldg_status ldg_set_c22(ldg_ctx c, double c22) {
+  if (!c) return LDG_E_INVALID;
+  if (!std::isfinite(c22) || c22 < 0.0) return fail(c, LDG_E_INVALID, "c22 must be finite and >= 0");
+  if (c22 != 0.0 && c->dc.EQ != LDG_POISSON)
+    return fail(c, LDG_E_UNSUPPORTED, "the coupled system with C22 != 0 is built for the Poisson equation");
+  c->dc.mp.c22 = c22;
+  return LDG_OK;
+}
+
 ldg_status ldg_set_preconditioner(ldg_ctx c, int32_t kind) {
   if (!c) return LDG_E_INVALID;
   if (kind != LDG_PRECOND_BILU0 && kind != LDG_PRECOND_BLOCK_LU) return fail(c, LDG_E_INVALID, "preconditioner kind");
@@ -412,64 +423,70 @@ ldg_status ldg_export_operators(ldg_ctx c, double* K11, double* K12, double* F) 
 }
 
 // ------------------------------------------------------------------ Krylov helpers
-static ldg_status dots(ldg_ctx c, const double* V, int k, const double* w, double* host_out) {
+// V_j . w for j < k (columns of length n, stored one after another), to the host
+static ldg_status dots(ldg_ctx c, int64_t n, const double* V, int k, const double* w, double* host_out) {
   const DevCtx& dc = c->dc;
-  HIPCK(c, launch_multidot(V, c->ndof, k, w, c->ndof, c->d_partial, c->nblk_dot, dc.stream));
+  HIPCK(c, launch_multidot(V, n, k, w, n, c->d_partial, c->nblk_dot, dc.stream));
   HIPCK(c, launch_multidot_finish(c->d_partial, c->nblk_dot, k, c->d_h, dc.stream));
   HIPCK(c, hipMemcpyAsync(host_out, c->d_h, sizeof(double) * k, hipMemcpyDeviceToHost, dc.stream));
   HIPCK(c, hipStreamSynchronize(dc.stream));
   return LDG_OK;
 }
 
-static ldg_status norm2(ldg_ctx c, const double* w, double* out) {
+static ldg_status norm2(ldg_ctx c, int64_t n, const double* w, double* out) {
   double v;
-  TRY(dots(c, w, 1, w, &v));
+  TRY(dots(c, n, w, 1, w, &v));
   *out = std::sqrt(v);
   return LDG_OK;
 }
 
-// Right-preconditioned GMRES(restart) on (alpha I - gamma A) x = b, x0 = 0,
-// classical Gram-Schmidt with a selective second pass.  The operator is the
-// stored split product (exact = false) or the exact tangent (exact = true).
-// true_res: end with the true residual ||b - A x|| in *est_res (else the
-// Arnoldi estimate; the refinement loop computes the exact residual itself).
-static ldg_status gmres(ldg_ctx c, const double* b, double* x, double rtol_abs, int restart, int max_iters,
-                        bool exact, int* iters, double* est_res, bool true_res = true) {
+// A linear system for GMRES: vectors of length n, the operator, the
+// preconditioner, and the work space (V: restart + 1 columns, Z: restart
+// columns, r and tmp: one each).
+struct KrylovSystem {
+  int64_t n;
+  double *V, *Z, *r, *tmp;
+  std::function<ldg_status(const double*, double*)> op, prec;
+};
+
+// Right-preconditioned GMRES(restart) on A x = b, x0 = 0, classical
+// Gram-Schmidt with a selective second pass.  true_res: end with the true
+// residual ||b - A x|| in *est_res (else the Arnoldi estimate; the refinement
+// loop computes the exact residual itself).
+static ldg_status gmres_on(ldg_ctx c, const KrylovSystem& K, const double* b, double* x, double rtol_abs, int restart,
+                           int max_iters, int* iters, double* est_res, bool true_res) {
   const DevCtx& dc = c->dc;
-  const int64_t n = c->ndof;
+  const int64_t n = K.n;
   HIPCK(c, hipMemsetAsync(x, 0, sizeof(double) * n, dc.stream));
   std::vector<double> H((restart + 1) * restart), cs(restart), sn(restart), g(restart + 1), h(restart + 1),
       h2(restart + 1), y(restart);
   int its = 0;
   double beta;
   // r = b - A x
-  HIPCK(c, hipMemcpyAsync(c->d_r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, dc.stream));
+  HIPCK(c, hipMemcpyAsync(K.r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, dc.stream));
   bool first = true;
   while (true) {
     if (!first) {
-      TRY(apply_op(c, x, c->d_tmp, exact));
-      HIPCK(c, hipMemcpyAsync(c->d_r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, dc.stream));
-      HIPCK(c, launch_axpby(c->d_r, -1.0, c->d_tmp, 1.0, n, dc.stream));
+      TRY(K.op(x, K.tmp));
+      HIPCK(c, hipMemcpyAsync(K.r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, dc.stream));
+      HIPCK(c, launch_axpby(K.r, -1.0, K.tmp, 1.0, n, dc.stream));
     }
     first = false;
-    TRY(norm2(c, c->d_r, &beta));
+    TRY(norm2(c, n, K.r, &beta));
     *est_res = beta;
     if (!std::isfinite(beta)) return fail(c, LDG_E_NONFINITE, "non-finite GMRES residual");
     if (beta <= rtol_abs || its >= max_iters) break;
-    HIPCK(c, hipMemcpyAsync(c->d_V, c->d_r, sizeof(double) * n, hipMemcpyDeviceToDevice, dc.stream));
-    HIPCK(c, launch_axpby(c->d_V, 0.0, c->d_r, 1.0 / beta, n, dc.stream));
+    HIPCK(c, hipMemcpyAsync(K.V, K.r, sizeof(double) * n, hipMemcpyDeviceToDevice, dc.stream));
+    HIPCK(c, launch_axpby(K.V, 0.0, K.r, 1.0 / beta, n, dc.stream));
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     int k_used = 0;
     for (int k = 0; k < restart; ++k) {
-      double* vk = c->d_V + (int64_t)k * n;
-      double* w = c->d_V + (int64_t)(k + 1) * n;
-      double* zk = c->d_Z + (int64_t)k * n;  // z_k = P^{-1} v_k is kept for the update of x
-      {
-        Span sp(c, 2);
-        TRY(precond_apply_any(c, vk, zk));
-      }
-      TRY(apply_op(c, zk, w, exact));
+      double* vk = K.V + (int64_t)k * n;
+      double* w = K.V + (int64_t)(k + 1) * n;
+      double* zk = K.Z + (int64_t)k * n;  // z_k = P^{-1} v_k is kept for the update of x
+      TRY(K.prec(vk, zk));
+      TRY(K.op(zk, w));
       // Classical Gram-Schmidt, repeated once when the projection removed more
       // than half of |w|^2 (the Daniel-Gragg-Kaufman-Stewart criterion with
       // eta = 1/sqrt 2).  w = V_{k+1} follows V_k in memory, so one pass gives
@@ -480,22 +497,22 @@ static ldg_status gmres(ldg_ctx c, const double* b, double* x, double rtol_abs, 
       std::fill(h2.begin(), h2.end(), 0.0);
       for (int pass = 0; pass < 2 && !done; ++pass) {
         double* hp = pass == 0 ? h.data() : h2.data();
-        TRY(dots(c, c->d_V, k + 2, w, hp));
+        TRY(dots(c, n, K.V, k + 2, w, hp));
         double hh = 0.0;
         for (int j = 0; j <= k; ++j) hh += hp[j] * hp[j];
         const double ww = hp[k + 1], rest = ww - hh;
         HIPCK(c, hipMemcpyAsync(c->d_h, hp, sizeof(double) * (k + 1), hipMemcpyHostToDevice, dc.stream));
         if (rest > 0.5 * ww) {
           hn = std::sqrt(rest);
-          HIPCK(c, launch_update(w, c->d_V, n, k + 1, c->d_h, n, dc.stream, 1.0 / hn));
+          HIPCK(c, launch_update(w, K.V, n, k + 1, c->d_h, n, dc.stream, 1.0 / hn));
           done = true;
         } else {
-          HIPCK(c, launch_update(w, c->d_V, n, k + 1, c->d_h, n, dc.stream));
+          HIPCK(c, launch_update(w, K.V, n, k + 1, c->d_h, n, dc.stream));
         }
       }
       if (!done) {
         // near breakdown (or non-finite values): the norm is taken explicitly
-        TRY(norm2(c, w, &hn));
+        TRY(norm2(c, n, w, &hn));
         if (hn > 0 && std::isfinite(hn)) HIPCK(c, launch_axpby(w, 0.0, w, 1.0 / hn, n, dc.stream));
       }
       for (int j = 0; j <= k; ++j) H[j * restart + k] = h[j] + h2[j];
@@ -526,19 +543,38 @@ static ldg_status gmres(ldg_ctx c, const double* b, double* x, double rtol_abs, 
     }
     // x += P^{-1} (V y) = Z y  (P^{-1} is linear and the z_k were kept)
     HIPCK(c, hipMemcpyAsync(c->d_h, y.data(), sizeof(double) * k_used, hipMemcpyHostToDevice, dc.stream));
-    HIPCK(c, launch_lincomb(x, c->d_Z, n, k_used, c->d_h, n, dc.stream));
+    HIPCK(c, launch_lincomb(x, K.Z, n, k_used, c->d_h, n, dc.stream));
     if ((*est_res <= rtol_abs || its >= max_iters) && !true_res) break;
     if (*est_res <= rtol_abs || its >= max_iters) {
       // true residual for the report
-      TRY(apply_op(c, x, c->d_tmp, exact));
-      HIPCK(c, hipMemcpyAsync(c->d_r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, dc.stream));
-      HIPCK(c, launch_axpby(c->d_r, -1.0, c->d_tmp, 1.0, n, dc.stream));
-      TRY(norm2(c, c->d_r, est_res));
+      TRY(K.op(x, K.tmp));
+      HIPCK(c, hipMemcpyAsync(K.r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, dc.stream));
+      HIPCK(c, launch_axpby(K.r, -1.0, K.tmp, 1.0, n, dc.stream));
+      TRY(norm2(c, n, K.r, est_res));
       break;
     }
   }
   *iters = its;
   return LDG_OK;
+}
+
+// GMRES on the Newton system (alpha I - gamma A) x = b: the stored split
+// product (exact = false) or the exact tangent (exact = true), preconditioned
+// by the assembled preconditioner.
+static ldg_status gmres(ldg_ctx c, const double* b, double* x, double rtol_abs, int restart, int max_iters,
+                        bool exact, int* iters, double* est_res, bool true_res = true) {
+  KrylovSystem K;
+  K.n = c->ndof;
+  K.V = c->d_V;
+  K.Z = c->d_Z;
+  K.r = c->d_r;
+  K.tmp = c->d_tmp;
+  K.op = [c, exact](const double* in, double* out) { return apply_op(c, in, out, exact); };
+  K.prec = [c](const double* in, double* out) {
+    Span sp(c, 2);
+    return precond_apply_any(c, in, out);
+  };
+  return gmres_on(c, K, b, x, rtol_abs, restart, max_iters, iters, est_res, true_res);
 }
 
 static ldg_status ensure_krylov(ldg_ctx c, int restart) {
@@ -567,6 +603,115 @@ static ldg_status ensure_krylov(ldg_ctx c, int restart) {
   return LDG_OK;
 }
 
+// Steady solve of the coupled (U, Q) system of a linear problem:
+// F(U, Q) = [-R(U, Q); Q - G(U, Q)] = 0 with G the gradient whose trace
+// carries the C22 jump.  Flexible GMRES on A [U; Q] = -F(0) with
+//   A [xU; xQ] = [-R_h(xU, xQ); xQ - G_h(xU, xQ)]        (h: no source, no boundary data),
+// preconditioned by an approximate inverse of the C22 = 0 matrix
+// A0 = [[-K11, -K12], [-K21, I]]: zU solves S zU = rU + K12 rQ with
+// S = -(K11 + K12 K21) by inner GMRES (the reduced system's operator and
+// element-block preconditioner) to inner_rtol, and zQ = rQ + K21 zU.  The
+// inner solve is needed: with zU = P^{-1} (rU + K12 rQ) for the element-block
+// P alone, the C22 coupling of neighbouring Q leaves A M^{-1} with eigenvalues
+// far in the left half plane and the iteration stalls.  The outer iteration
+// keeps z_k = M^{-1} v_k, so a preconditioner that changes from one
+// application to the next is allowed.
+static ldg_status coupled_solve(ldg_ctx c, double* U, double* Q, double rtol, double inner_rtol, int restart,
+                                int max_iters, int* iters, int* inner_iters, double* relres) {
+  const DevCtx& dc = c->dc;
+  const int64_t nu = c->ndof, nq = c->nq, N = nu + nq;
+  TRY(ensure_krylov(c, restart));  // the inner solves use the reduced system's Krylov space
+  // work: V (restart + 1) N, Z restart N, r, tmp, b, x (N each), zero (N), t (nu)
+  const size_t need = (size_t)(2 * restart + 6) * N + nu;
+  TRY(grow(c, (void**)&c->d_cwork, &c->cap_cwork, sizeof(double) * need));
+  double* V = c->d_cwork;
+  double* Z = V + (size_t)(restart + 1) * N;
+  double* r = Z + (size_t)restart * N;
+  double* tmp = r + N;
+  double* b = tmp + N;
+  double* x = b + N;
+  double* zero = x + N;
+  double* t = zero + N;
+  HIPCK(c, hipMemsetAsync(zero, 0, sizeof(double) * N, dc.stream));
+  // K11, K12, K21 weights and the preconditioner of S: alpha = 0, gamma = 1
+  TRY(assemble(c, zero, 0.0, 1.0, LDG_F64, nullptr));
+  // b = -F(0) = [R(0, 0); G(0, 0)]
+  HIPCK(c, launch_residual(dc, zero, zero + nu, b));
+  HIPCK(c, launch_gradient(dc, zero, b + nu, false, zero + nu));
+  DevCtx dh = dc;
+  dh.mp.S = nullptr;
+  dh.mp.gD = nullptr;
+  dh.mp.gN = nullptr;
+  KrylovSystem K;
+  K.n = N;
+  K.V = V;
+  K.Z = Z;
+  K.r = r;
+  K.tmp = tmp;
+  K.op = [c, dh, nu, nq](const double* in, double* out) -> ldg_status {
+    HIPCK(c, launch_residual(dh, in, in + nu, out));
+    HIPCK(c, launch_axpby(out, 0.0, out, -1.0, nu, dh.stream));
+    HIPCK(c, launch_gradient(dh, in, out + nu, true, in + nu));
+    HIPCK(c, launch_axpby(out + nu, 1.0, in + nu, -1.0, nq, dh.stream));
+    return LDG_OK;
+  };
+  int inner_total = 0;
+  K.prec = [c, nu, nq, zero, t, inner_rtol, restart, &inner_total](const double* in, double* out) -> ldg_status {
+    const DevCtx& d = c->dc;
+    // t = rU + K12 rQ (the split product with alpha = 0, gamma = 1 and x = 0 gives -K12 rQ)
+    HIPCK(c, launch_jacvec(d, c->d_K11, c->d_K12, LDG_F64, 0.0, 1.0, zero, in + nu, t));
+    HIPCK(c, launch_axpby(t, 1.0, in, -1.0, nu, d.stream));
+    double tn = 0.0, est = 0.0;
+    TRY(norm2(c, nu, t, &tn));
+    int its = 0;
+    if (tn > 0.0) {
+      TRY(gmres(c, t, out, inner_rtol * tn, restart, restart, false, &its, &est, false));
+    } else {
+      HIPCK(c, hipMemsetAsync(out, 0, sizeof(double) * nu, d.stream));
+    }
+    inner_total += its;
+    HIPCK(c, launch_k21_apply(d, c->d_K21w, out, out + nu));
+    HIPCK(c, launch_axpby(out + nu, 1.0, in + nu, 1.0, nq, d.stream));
+    return LDG_OK;
+  };
+  double bn = 0.0, res = 0.0;
+  TRY(norm2(c, N, b, &bn));
+  if (!std::isfinite(bn)) return fail(c, LDG_E_NONFINITE, "non-finite right-hand side");
+  int its = 0;
+  if (bn == 0.0) {
+    HIPCK(c, hipMemsetAsync(x, 0, sizeof(double) * N, dc.stream));
+  } else {
+    const ldg_status st = gmres_on(c, K, b, x, rtol * bn, restart, max_iters, &its, &res, true);
+    c->krylov_avail = 0;  // the Arnoldi vectors left are those of an inner solve
+    TRY(st);
+  }
+  HIPCK(c, hipMemcpyAsync(U, x, sizeof(double) * nu, hipMemcpyDeviceToDevice, dc.stream));
+  HIPCK(c, hipMemcpyAsync(Q, x + nu, sizeof(double) * nq, hipMemcpyDeviceToDevice, dc.stream));
+  HIPCK(c, hipStreamSynchronize(dc.stream));
+  *iters = its;
+  *inner_iters = inner_total;
+  *relres = bn > 0 ? res / bn : 0.0;
+  if (bn > 0 && !(res <= rtol * bn)) return fail(c, LDG_E_NOT_CONVERGED, "coupled GMRES did not reach rtol");
+  return LDG_OK;
+}
+
+ldg_status ldg_coupled_solve(ldg_ctx c, double* U, double* Q, double rtol, double inner_rtol, int32_t restart,
+                             int32_t max_iters, int32_t* iters, int32_t* inner_iters, double* relres) {
+  if (!c) return LDG_E_INVALID;
+  if (!U || !Q) return fail(c, LDG_E_INVALID, "null pointer");
+  if ((const void*)U == (const void*)Q) return fail(c, LDG_E_INVALID, "U and Q alias");
+  if (c->dc.EQ != LDG_POISSON) return fail(c, LDG_E_UNSUPPORTED, "the coupled solve is built for the Poisson equation");
+  if (!(rtol > 0.0) || !(inner_rtol > 0.0) || !(inner_rtol < 1.0) || restart < 1 || restart > 120 || max_iters < 1)
+    return fail(c, LDG_E_INVALID, "rtol > 0, 0 < inner_rtol < 1, restart in 1..120, max_iters >= 1");
+  int its = 0, inner = 0;
+  double rr = 0.0;
+  const ldg_status st = coupled_solve(c, U, Q, rtol, inner_rtol, restart, max_iters, &its, &inner, &rr);
+  if (iters) *iters = its;
+  if (inner_iters) *inner_iters = inner;
+  if (relres) *relres = rr;
+  return st;
+}
+
 // G(U) = alpha (U - Ucomb) - gamma R(U) into G (R(U) into d_R) and ||G||_2.
 static ldg_status eval_G(ldg_ctx c, const double* U, const double* Ucomb, double alpha, double gamma, double* G,
                          double* gnorm) {
@@ -576,7 +721,7 @@ static ldg_status eval_G(ldg_ctx c, const double* U, const double* Ucomb, double
   HIPCK(c, launch_copy(G, U, n, dc.stream));
   if (Ucomb) HIPCK(c, launch_axpby(G, -1.0, Ucomb, 1.0, n, dc.stream));
   HIPCK(c, launch_axpby(G, -gamma, c->d_R, alpha, n, dc.stream));
-  TRY(norm2(c, G, gnorm));
+  TRY(norm2(c, c->ndof, G, gnorm));
   return LDG_OK;
 }
 
@@ -627,7 +772,7 @@ static ldg_status linear_solve(ldg_ctx c, const ldg_solver_opts* o, const Newton
     TRY(apply_op(c, xacc, c->d_tmp, true));
     HIPCK(c, hipMemcpyAsync(rr, c->d_G, sizeof(double) * n, hipMemcpyDeviceToDevice, dc.stream));
     HIPCK(c, launch_axpby(rr, -1.0, c->d_tmp, 1.0, n, dc.stream));
-    TRY(norm2(c, rr, &rn));
+    TRY(norm2(c, c->ndof, rr, &rn));
     if (!std::isfinite(rn)) return fail(c, LDG_E_NONFINITE, "non-finite refinement residual");
     if (rn <= target) {
       ++sweeps;
@@ -670,7 +815,7 @@ static ldg_status newton_core(ldg_ctx c, double* U, const double* Ucomb, double 
   HIPCK(c, hipEventRecord(ev[0], dc.stream));
   double g0;
   if (ctl.G_current)
-    TRY(norm2(c, c->d_G, &g0));
+    TRY(norm2(c, c->ndof, c->d_G, &g0));
   else
     TRY(eval_G(c, U, Ucomb, alpha, gamma, c->d_G, &g0));
   HIPCK(c, hipEventRecord(ev[1], dc.stream));

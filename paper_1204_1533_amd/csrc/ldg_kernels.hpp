@@ -106,7 +106,10 @@ struct FacShape {
   static constexpr int NT = (EPB * NR + 63) / 64 * 64;
 };
 
-hipError_t launch_gradient(const DevCtx& c, const double* U, double* Q, bool homogeneous);
+// Q = D(U); with Qc (C22 != 0, the coupled system) the trace takes the jump of
+// the normal viscous flux of the gradient field Qc: Q = G(U, Qc)
+hipError_t launch_gradient(const DevCtx& c, const double* U, double* Q, bool homogeneous,
+                           const double* Qc = nullptr);
 hipError_t launch_residual(const DevCtx& c, const double* U, const double* Q, double* R);
 // Rt = dR/dU . V (exact forward-mode tangent) with Qt = D_hom(V)
 hipError_t launch_residual_tangent(const DevCtx& c, const double* U, const double* V, const double* Q,

@@ -95,6 +95,10 @@ _SIGS = {
     "ldg_set_source": (ctypes.c_int, [_P, _P]),
     "ldg_set_dirichlet": (ctypes.c_int, [_P, _P]),
     "ldg_set_neumann": (ctypes.c_int, [_P, _P]),
+    "ldg_set_c22": (ctypes.c_int, [_P, ctypes.c_double]),
+    "ldg_coupled_solve": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                         ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
     "ldg_gradient": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32]),
     "ldg_residual": (ctypes.c_int, [_P, _P, _P, _P]),
     "ldg_jacobian_assemble": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_int32]),
@@ -236,6 +240,19 @@ class Context:
 
     def ldg_set_neumann(self, gN):
         self._check(self.lib.ldg_set_neumann(self.h, _ptr(gN)))
+
+    def ldg_set_c22(self, c22):
+        self._check(self.lib.ldg_set_c22(self.h, float(c22)))
+
+    def ldg_coupled_solve(self, U, Q, rtol=1e-10, inner_rtol=1e-2, restart=60, max_iters=500, raise_on_error=True):
+        its = ctypes.c_int32(0)
+        inner = ctypes.c_int32(0)
+        rr = ctypes.c_double(0.0)
+        st = self.lib.ldg_coupled_solve(self.h, _ptr(U), _ptr(Q), float(rtol), float(inner_rtol), int(restart),
+                                        int(max_iters), ctypes.byref(its), ctypes.byref(inner), ctypes.byref(rr))
+        if raise_on_error:
+            self._check(st)
+        return {"status": st, "iters": int(its.value), "inner_iters": int(inner.value), "relres": float(rr.value)}
 
     def ldg_gradient(self, U, Q, homogeneous=False):
         self._check(self.lib.ldg_gradient(self.h, _ptr(U), _ptr(Q), int(homogeneous)))
