@@ -591,6 +591,152 @@ __global__ void __launch_bounds__((factor_threads<D, P, EQ>())) factor_kernel(in
   }
 }
 
+// Block ILU(0) in FP32 working precision with each row in registers.  Work
+// item (row node i, component c) of the current level loads row c of its
+// node's line blocks once into registers: R[n][t] is the block of the node at
+// position t of its direction-n line (the entry t = c_n, the node itself, is
+// unused), Dg the diagonal block, shared by all D lines.  The elimination then
+// touches memory only to read the finished rows k of earlier levels (their
+// U diagonal inverse and right blocks), which no work item of the current
+// level writes, so those loads carry no dependence on the row being
+// eliminated.  Same operations in the same order as factor_kernel (FP64
+// arithmetic on FP32 values), so the factors are the same.  Finished blocks go
+// straight into the apply layout (precision FPOUT); of the element-major rows
+// only the U parts, which later levels read, are written back.
+template <int NR>
+__device__ __forceinline__ int fac_off(int r, int j) {
+  return ((j >> 2) * NR + r) * 4 + (j & 3);
+}
+template <int D, int P, int EQ, int FPOUT>
+__global__ void __launch_bounds__((factor_threads<D, P, EQ>())) __attribute__((amdgpu_waves_per_eu(4)))
+factor_reg_kernel(LevelOrder ord, float* __restrict__ F,
+                                                                                void* __restrict__ Fem) {
+  constexpr int N1 = P + 1, NP = ipow(N1, D), M = Eq<D, EQ>::M;
+  constexpr int NT = factor_threads<D, P, EQ>();
+  constexpr int RPP = NT / M;  // rows per pass
+  constexpr int NSLMM = (D * P + 1) * M * M;
+  constexpr int NR = NP * M, NJ = (D * P + 1) * M, NJP = (NJ + 3) / 4 * 4;
+  __shared__ double sBlk[RPP][M][M];  // diagonal blocks of the pass's nodes
+  const int64_t e = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int gi = lane / M, c = lane % M;
+  for (int L = 0; L <= D * P; ++L) {
+    const int nrow = ord.off[L + 1] - ord.off[L];
+    for (int r0 = 0; r0 < nrow; r0 += RPP) {
+      const bool active = (lane < RPP * M) && r0 + gi < nrow;
+      const int i = active ? ord.node[ord.off[L] + r0 + gi] : 0;
+      int cd[D], lev = 0;
+#pragma unroll
+      for (int d = 0, r = i; d < D; ++d, r /= N1) {
+        cd[d] = r % N1;
+        lev += cd[d];
+      }
+      float* row = F + (e * NP + i) * NSLMM;
+      const int rbase = M * (ord.off[L] + r0 + gi);  // apply-layout row of component 0 of node i
+      // the element's factor rows: entry j of row r at ((j / 4) NR + r) 4 + j % 4
+      void* fe = static_cast<char*>(Fem) + sizeof(typename Store<FPOUT>::type) * (size_t)(e * NR * NJP);
+      if (active) {
+        // the blocks of one direction's line change only while that direction
+        // is eliminated: one line in registers at a time, the diagonal throughout
+        float Dg[M];
+#pragma unroll
+        for (int q = 0; q < M; ++q) Dg[q] = row[(cd[0] * M + c) * M + q];
+#pragma unroll
+        for (int n = 0; n < D; ++n) {
+          float R[N1][M];
+#pragma unroll
+          for (int t = 0; t < N1; ++t) {
+            const int slot = n == 0 ? t : N1 + (n - 1) * P + (t < cd[n] ? t : t - 1);
+#pragma unroll
+            for (int q = 0; q < M; ++q) R[t][q] = t != cd[n] ? row[(slot * M + c) * M + q] : 0.0f;
+          }
+          int stride = 1;
+#pragma unroll
+          for (int d = 0; d < n; ++d) stride *= N1;
+#pragma unroll
+          for (int tk = 0; tk < P; ++tk) {
+            if (tk < cd[n]) {
+              const int k = i + (tk - cd[n]) * stride;
+              const int self_k = n == 0 ? tk : cd[0];
+              const float* krow = F + (e * NP + k) * NSLMM;
+              // L_ik[c][:] = A_ik[c][:] Uinv_kk
+              double lrow[M];
+#pragma unroll
+              for (int j = 0; j < M; ++j) {
+                double s = 0.0;
+#pragma unroll
+                for (int q = 0; q < M; ++q) s += (double)R[tk][q] * (double)krow[(self_k * M + q) * M + j];
+                lrow[j] = s;
+              }
+#pragma unroll
+              for (int j = 0; j < M; ++j) R[tk][j] = (float)lrow[j];
+              // A_ij -= L_ik U_kj for j after k on the line (the diagonal when t_j = c_n)
+#pragma unroll
+              for (int tj = tk + 1; tj < N1; ++tj) {
+                const int skj = n == 0 ? tj : N1 + (n - 1) * P + tj - 1;
+                const bool diag = tj == cd[n];
+#pragma unroll
+                for (int j = 0; j < M; ++j) {
+                  double s = 0.0;
+#pragma unroll
+                  for (int q = 0; q < M; ++q) s += lrow[q] * (double)krow[(skj * M + q) * M + j];
+                  const float v = (float)((double)(diag ? Dg[j] : R[tj][j]) - s);
+                  if (diag)
+                    Dg[j] = v;
+                  else
+                    R[tj][j] = v;
+                }
+              }
+            }
+          }
+          // this line's L and U blocks are final: row positions (left blocks
+          // of the earlier directions, then this line's; right blocks after
+          // the diagonal likewise)
+          int left = 0, right = lev + 1;
+#pragma unroll
+          for (int m = 0; m < n; ++m) {
+            left += cd[m];
+            right += P - cd[m];
+          }
+#pragma unroll
+          for (int t = 0; t < N1; ++t) {
+            const int slot = n == 0 ? t : N1 + (n - 1) * P + (t < cd[n] ? t : t - 1);
+            if (t != cd[n]) {
+              const int pos = t < cd[n] ? left + t : right + t - cd[n] - 1;
+#pragma unroll
+              for (int q = 0; q < M; ++q) {
+                Store<FPOUT>::put(fe, fac_off<NR>(rbase + c, pos * M + q), R[t][q]);
+                if (t > cd[n]) row[(slot * M + c) * M + q] = R[t][q];
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int j = NJ; j < NJP; ++j) Store<FPOUT>::put(fe, fac_off<NR>(rbase + c, j), 0.0);
+#pragma unroll
+        for (int q = 0; q < M; ++q) sBlk[gi][c][q] = Dg[q];
+      }
+      __syncthreads();
+      // inverse of the U diagonal block: work item c takes column c
+      if (active) {
+        double A[M][M], xcol[M];
+#pragma unroll
+        for (int a = 0; a < M; ++a)
+#pragma unroll
+          for (int b = 0; b < M; ++b) A[a][b] = sBlk[gi][a][b];
+        solve_unit_column<M>(A, c, xcol);
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+          const float v = (float)xcol[a];
+          row[(cd[0] * M + a) * M + c] = v;
+          Store<FPOUT>::put(fe, fac_off<NR>(rbase + a, lev * M + c), v);
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // Registers of one factor row: NJP entries of precision FP, loaded 4 at a time
 // (8 bytes for BF16, 16 for FP32, 32 for FP64) from the apply layout.
 template <int FP, int NJP> struct RowRegs;
@@ -976,14 +1122,12 @@ hipError_t launch_precond_factor(const DevCtx& dc, const void* K11, const void* 
           hipLaunchKernelGGL((relayout_kernel<PREC_F32>), tgrid, dim3(256), 0, dc.stream, Fwork, em, NN, nq);
         }
         if (dense) return launch_blocklu_factor(dc, em, PREC_F32, dense);
-        hipLaunchKernelGGL((factor_kernel<D, P, EQ, PREC_F32>), dim3((unsigned)dc.E), dim3(factor_threads<D, P, EQ>()), 0,
-                           dc.stream, dc.E, em);
         if (fprec == PREC_BF16)
-          hipLaunchKernelGGL((em_to_fac_kernel<PREC_F32, PREC_BF16>), dim3(copy_grid(nFac / 4)), dim3(256), 0, dc.stream,
-                             dc.lev, em, Fem, dc.E, dc.NP, dc.M, nsl, dc.D, dc.P);
+          hipLaunchKernelGGL((factor_reg_kernel<D, P, EQ, PREC_BF16>), dim3((unsigned)dc.E),
+                             dim3(factor_threads<D, P, EQ>()), 0, dc.stream, dc.lev, em, Fem);
         else
-          hipLaunchKernelGGL((em_to_fac_kernel<PREC_F32, PREC_F32>), dim3(copy_grid(nFac / 4)), dim3(256), 0, dc.stream,
-                             dc.lev, em, Fem, dc.E, dc.NP, dc.M, nsl, dc.D, dc.P);
+          hipLaunchKernelGGL((factor_reg_kernel<D, P, EQ, PREC_F32>), dim3((unsigned)dc.E),
+                             dim3(factor_threads<D, P, EQ>()), 0, dc.stream, dc.lev, em, Fem);
       }
       return hipGetLastError();
     })
