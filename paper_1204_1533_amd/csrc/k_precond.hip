@@ -8,16 +8,12 @@
 //           wavefront reads contiguous memory for every (slot, c, c')); the
 //           workgroup holds whole elements and stages their x and w in LDS.
 // form:     A~ = alpha I - gamma (K11 + K12 K21) restricted to the D lines
-//           through each node, K21 taken inside the element.  The K21 weights
-//           of a direction-n line are the scalar line operator
-//             G[t][t'][d] = -sum_g V_tg I_gt' a_n(x_g)_d + L1_t n^+_d [t'=p, inside]
-//                           + L0_t n^-_d [t'=0, inside]
-//           (inside: the switch takes the trace from this element), divided
-//           by J of the node t.  For a row a and a column b on its
-//           direction-n line, (K12 K21)_ab = sum_{c on that line} K12_ac W_cb,
-//           with W_cb = G_n[t_c][t_b] / J_c for c != b and W_bb the sum of the
-//           diagonal entries of all D line operators through b over J_b; for
-//           b = a the sum over c runs over all D lines.
+//           through each node, K21 taken inside the element from its stored
+//           weights: for a row a and a column b on its direction-n line,
+//           (K12 K21)_ab = sum_{c on that line} K12_ac W_cb, with W_cb the
+//           weight of row c at its slot of column b (for c = b the self slot,
+//           which sums the D lines through b); for b = a the sum over c runs
+//           over all D lines.
 // factor:   block ILU(0) in natural node order.  Row i depends only on the
 //           earlier nodes of its own lines, so rows with equal i+j(+k) form
 //           independent levels; each row's lower blocks k update only blocks
@@ -145,143 +141,43 @@ hipError_t launch_jacvec(const DevCtx& dc, const void* K11, const void* K12, int
 }
 
 // --------------------------------------------------------------------------- formation of A~
-template <int D, int P, int EQ>
-struct FormLayout {
-  static constexpr int N1 = P + 1, NG = n_gauss(P), NP = ipow(N1, D), NL = ipow(N1, D - 1);
-  static constexpr int oX = 0;
-  static constexpr int oG = oX + D * NP;
-  static constexpr int oJ = oG + D * D * NP;
-  static constexpr int oAg = oJ + NP;
-  static constexpr int oN = oAg + D * NL * NG * D;
-  static constexpr int oW = oN + D * NL * 2 * D;
-  static constexpr int oS = oW + D * NL * N1 * N1 * D;
-  static constexpr int ndoubles = oS + NP * D;
-  static constexpr size_t bytes = sizeof(double) * ndoubles;
-};
-
-// Writes A~ (line slots) in the working precision WP of the factorisation,
-// node-fastest [slot][c][c'][E*Np] (EM = false) or element-major
-// [E*Np][slot][c][c'] (EM = true: each element's rows are written by one
-// workgroup, so the region is complete in the cache before it is written back).
+// Writes A~ = alpha I - gamma (K11 + K12 K21) on the line pattern in the
+// working precision WP of the factorisation, node-fastest [slot][c][c'][E*Np]
+// (EM = false) or element-major [E*Np][slot][c][c'] (EM = true).  K21 comes
+// from its stored weights (row node, slot, d), the element's copied to LDS,
+// so no geometry is recomputed.  One work item per (row node a, row component
+// c); for each of the D lines through a, row c of K12 on the line's p+1 slots
+// is loaded once and gives the p+1 output blocks on that line:
+//   (K12 K21)_ab[c][k] = sum_{c' on the line, c' != b} K12_ac'[c][k,:] . W21(c' -> b)
+//                      + K12_ab[c][k,:] . W21(b -> b)
+// (W21(c' -> b): the weights of row c' at its slot of column b; W21(b -> b)
+// the self slot, which sums b's D lines).  The self block (b = a) collects the
+// c' != a terms of all D lines.
+template <int D, int P>
+__host__ __device__ constexpr size_t form_lds_bytes() {
+  return sizeof(double) * (size_t)(D * P + 1) * D * ipow(P + 1, D);
+}
 template <int D, int P, int EQ, int PR, int WP, bool EM>
-__global__ void __launch_bounds__(NT_ELEM) form_kernel(LineOps ops, MeshParams mp, const void* __restrict__ K11,
-                                                       const void* __restrict__ K12, double alpha, double gamma,
-                                                       void* __restrict__ F) {
-  using L = FormLayout<D, P, EQ>;
-  constexpr int N1 = L::N1, NG = L::NG, NP = L::NP, NL = L::NL, M = Eq<D, EQ>::M;
+__global__ void __launch_bounds__(NT_ELEM) form_kernel(MeshParams mp, const void* __restrict__ K11,
+                                                       const void* __restrict__ K12, const double* __restrict__ W21,
+                                                       double alpha, double gamma, void* __restrict__ F) {
+  constexpr int N1 = P + 1, NP = ipow(N1, D), M = Eq<D, EQ>::M;
   constexpr bool VIS = Eq<D, EQ>::VIS;
   constexpr int NSL = D * P + 1, MD = M * D;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* sm = reinterpret_cast<double*>(smem_raw);
-  double* sX = sm + L::oX;
-  double* sG = sm + L::oG;
-  double* sJ = sm + L::oJ;
-  double* sAg = sm + L::oAg;
-  double* sN = sm + L::oN;
-  double* sW = sm + L::oW;
-  double* sS = sm + L::oS;  // full K21 self weight of each node: sum over its D lines, divided by J
+  double* sK = reinterpret_cast<double*>(smem_raw);  // [line slot][d][node] of this element
   const int64_t e = blockIdx.x;
-  const int tid = threadIdx.x;
   const int64_t NN = mp.E * NP;
   if constexpr (VIS) {
-    for (int i = tid; i < D * NP; i += NT_ELEM) sX[i] = mp.xyz[e * D * NP + i];
-    __syncthreads();
-    for (int i = tid; i < D * D * NP; i += NT_ELEM) {
-      const int ab = i / NP, node = i % NP;
-      const int a = ab / D, b = ab % D;
-      int s = 1;
-      for (int k = 0; k < b; ++k) s *= N1;
-      const int tb = (node / s) % N1;
-      double acc = 0.0;
-#pragma unroll
-      for (int q = 0; q < N1; ++q) acc += ops.Dn[tb][q] * sX[a * NP + node - tb * s + q * s];
-      sG[ab * NP + node] = acc;
-    }
-    __syncthreads();
-    for (int i = tid; i < NP; i += NT_ELEM) {
-      double G[D][D];
-#pragma unroll
-      for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int b = 0; b < D; ++b) G[a][b] = sG[(a * D + b) * NP + i];
-      sJ[i] = 1.0 / det<D>(G);
-    }
-    for (int it = tid; it < D * NL * NG; it += NT_ELEM) {
-      const int n = it / (NL * NG), l = (it / NG) % NL, g = it % NG;
-      double G[D][D], an[D];
-#pragma unroll
-      for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int b = 0; b < D; ++b) {
-          double acc = 0.0;
-          if (b == n) {
-#pragma unroll
-            for (int t = 0; t < N1; ++t) acc += ops.Dg[g][t] * sX[a * NP + line_node<D, N1>(n, l, t)];
-          } else {
-#pragma unroll
-            for (int t = 0; t < N1; ++t) acc += ops.I[g][t] * sG[(a * D + b) * NP + line_node<D, N1>(n, l, t)];
-          }
-          G[a][b] = acc;
-        }
-      cofactor_row<D>(G, n, an);
-#pragma unroll
-      for (int d = 0; d < D; ++d) sAg[it * D + d] = an[d];
-    }
-    for (int it = tid; it < D * NL * 2; it += NT_ELEM) {
-      const int n = it / (NL * 2), l = (it / 2) % NL, s = it % 2;
-      const int nin = line_node<D, N1>(n, l, s ? P : 0);
-      double G[D][D], an[D];
-#pragma unroll
-      for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int b = 0; b < D; ++b) G[a][b] = sG[(a * D + b) * NP + nin];
-      cofactor_row<D>(G, n, an);
-#pragma unroll
-      for (int d = 0; d < D; ++d) sN[it * D + d] = s ? an[d] : -an[d];
-    }
-    __syncthreads();
-    // scalar K21 line operators G_n[l][t][t'][d] (without the 1/J of row t)
-    for (int it = tid; it < D * NL * N1 * N1 * D; it += NT_ELEM) {
-      const int d = it % D;
-      const int tp = (it / D) % N1;
-      const int t = (it / (D * N1)) % N1;
-      const int l = (it / (D * N1 * N1)) % NL;
-      const int n = it / (D * N1 * N1 * NL);
-      double v = 0.0;
-#pragma unroll
-      for (int g = 0; g < NG; ++g) v -= ops.V[t][g] * ops.I[g][tp] * sAg[((n * NL + l) * NG + g) * D + d];
-      // the trace is taken inside: switch +1 on an interior face, or a Neumann face / slip wall
-      const int Sp = mp.sw[e * D + n];
-      const int k1 = face_kind(mp.face_nbr[e * 2 * D + 2 * n + 1]), k0 = face_kind(mp.face_nbr[e * 2 * D + 2 * n]);
-      if (tp == P && ((Sp > 0 && k1 == BC_INTERIOR) || k1 == BC_NEUMANN || k1 == BC_SLIP))
-        v += ops.L1[t] * sN[((n * NL + l) * 2 + 1) * D + d];
-      if (tp == 0 && ((Sp < 0 && k0 == BC_INTERIOR) || k0 == BC_NEUMANN || k0 == BC_SLIP))
-        v += ops.L0[t] * sN[((n * NL + l) * 2 + 0) * D + d];
-      sW[it] = v;
-    }
-    __syncthreads();
-    for (int it = tid; it < NP * D; it += NT_ELEM) {
-      const int b = it / D, d = it % D;
-      double v = 0.0;
-#pragma unroll
-      for (int m = 0; m < D; ++m) {
-        int lm, tm;
-        node_line<N1>(b, m, lm, tm);
-        v += sW[(((m * NL + lm) * N1 + tm) * N1 + tm) * D + d];
-      }
-      sS[it] = v * sJ[b];
+    for (int i = threadIdx.x; i < NSL * D * NP; i += NT_ELEM) {
+      const int sd = i / NP, node = i % NP;
+      sK[i] = W21[sd * NN + e * NP + node];
     }
     __syncthreads();
   }
-  // A~ rows: one work item per (row node a, row component c).  For each of the
-  // D lines through a, row c of K12 on the line's p+1 slots is loaded once and
-  // gives the p+1 output blocks on that line:
-  //   (K12 K21)_ab[c][k] = sum_{c' on the line, c' != b} K12_ac'[c][k,:] . W_n[t_c'][t_b][:] / J_c'
-  //                      + K12_ab[c][k,:] . S_b[:]        (S_b: self weight of b over its D lines)
-  // The self block (b = a) collects the c' != a terms of all D lines.
   using KT = typename std::conditional<PR == PREC_F64, double, float>::type;
 #pragma unroll 1
-  for (int it = tid; it < NP * M; it += NT_ELEM) {
+  for (int it = threadIdx.x; it < NP * M; it += NT_ELEM) {
     const int a = it % NP, c = it / NP;
     const int self = a % N1;
     const int64_t gn = e * NP + a;
@@ -293,14 +189,12 @@ __global__ void __launch_bounds__(NT_ELEM) form_kernel(LineOps ops, MeshParams m
       int la, ta;
       node_line<N1>(a, n, la, ta);
       KT kc[VIS ? N1 : 1][VIS ? MD : 1];
-      double jc[N1];
       if constexpr (VIS) {
 #pragma unroll
         for (int tc = 0; tc < N1; ++tc) {
           const int sc = slot_of<N1>(n, ta, tc, self);
 #pragma unroll
           for (int q = 0; q < MD; ++q) kc[tc][q] = (KT)Store<PR>::get(K12, ((int64_t)(sc * M + c) * MD + q) * NN + gn);
-          jc[tc] = sJ[line_node<D, N1>(n, la, tc)];
         }
       }
 #pragma unroll
@@ -315,9 +209,11 @@ __global__ void __launch_bounds__(NT_ELEM) form_kernel(LineOps ops, MeshParams m
 #pragma unroll
           for (int tc = 0; tc < N1; ++tc) {
             if (tc == tb) continue;
+            const int cn = line_node<D, N1>(n, la, tc);
+            const int sw = slot_of<N1>(n, tc, tb, cn % N1);  // column b in row c''s slots
             double w[D];
 #pragma unroll
-            for (int d = 0; d < D; ++d) w[d] = sW[(((n * NL + la) * N1 + tc) * N1 + tb) * D + d] * jc[tc];
+            for (int d = 0; d < D; ++d) w[d] = sK[(sw * D + d) * NP + cn];
 #pragma unroll
             for (int k = 0; k < M; ++k)
 #pragma unroll
@@ -333,7 +229,7 @@ __global__ void __launch_bounds__(NT_ELEM) form_kernel(LineOps ops, MeshParams m
 #pragma unroll
           for (int k = 0; k < M; ++k)
 #pragma unroll
-            for (int d = 0; d < D; ++d) prod[k] += (double)kc[tb][k * D + d] * sS[b * D + d];
+            for (int d = 0; d < D; ++d) prod[k] += (double)kc[tb][k * D + d] * sK[((b % N1) * D + d) * NP + b];
         }
         const int slot = slot_of<N1>(n, ta, tb, self);
 #pragma unroll
@@ -344,14 +240,14 @@ __global__ void __launch_bounds__(NT_ELEM) form_kernel(LineOps ops, MeshParams m
         }
       }
     }
-    // self block: K11 + the c' != a terms of all lines + K12_aa . S_a
+    // self block: K11 + the c' != a terms of all lines + K12_aa . W21(a -> a)
 #pragma unroll
     for (int k = 0; k < M; ++k) {
       double v = Store<PR>::get(K11, ((int64_t)(self * M + c) * M + k) * NN + gn) + self_acc[k];
       if constexpr (VIS) {
 #pragma unroll
         for (int d = 0; d < D; ++d)
-          v += Store<PR>::get(K12, ((int64_t)(self * M + c) * MD + k * D + d) * NN + gn) * sS[a * D + d];
+          v += Store<PR>::get(K12, ((int64_t)(self * M + c) * MD + k * D + d) * NN + gn) * sK[(self * D + d) * NP + a];
       }
       v = -gamma * v;
       if (c == k) v += alpha;
@@ -1071,8 +967,9 @@ static unsigned copy_grid(int64_t n) {
 // otherwise), then rearranged into the apply layout in Fem in storage
 // precision fprec.  With dense != null the element-major A~ is instead
 // expanded and factorised exactly (dense [E][NR][NR] LU in FP64).
-hipError_t launch_precond_factor(const DevCtx& dc, const void* K11, const void* K12, int prec, double alpha,
-                                 double gamma, void* Fwork, int fprec, void* Fem, float* At_copy, double* dense) {
+hipError_t launch_precond_factor(const DevCtx& dc, const void* K11, const void* K12, const double* K21w, int prec,
+                                 double alpha, double gamma, void* Fwork, int fprec, void* Fem, float* At_copy,
+                                 double* dense) {
   const int64_t NN = dc.E * dc.NP;
   const int nsl = dc.D * dc.P + 1;
   const int nq = nsl * dc.M * dc.M;
@@ -1081,9 +978,9 @@ hipError_t launch_precond_factor(const DevCtx& dc, const void* K11, const void* 
   const int64_t nFac = dc.E * (int64_t)NR * NJP;
   const dim3 tgrid((unsigned)((NN + 63) / 64), (unsigned)((nq + 31) / 32));
   LDG_DISPATCH(dc, {
-    using L = FormLayout<D, P, EQ>;
-    static_assert(L::bytes <= LDS_PER_CU, "formation workspace must fit one CU's LDS");
-    const size_t bytes = Eq<D, EQ>::VIS ? L::bytes : 0;
+    static_assert(form_lds_bytes<D, P>() <= LDS_PER_CU, "the element's K21 weights must fit one CU's LDS");
+    const size_t bytes = Eq<D, EQ>::VIS ? form_lds_bytes<D, P>() : 0;
+    if (Eq<D, EQ>::VIS && !K21w) return hipErrorInvalidValue;
     LDG_PREC_DISPATCH(prec, {
       if (fprec == PREC_F64) {
         double* em = (double*)Fwork + nF;
@@ -1093,7 +990,7 @@ hipError_t launch_precond_factor(const DevCtx& dc, const void* K11, const void* 
               hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
           if (err != hipSuccess) return err;
         }
-        hipLaunchKernelGGL(k, dim3((unsigned)dc.E), dim3(NT_ELEM), bytes, dc.stream, dc.ops, dc.mp, K11, K12, alpha,
+        hipLaunchKernelGGL(k, dim3((unsigned)dc.E), dim3(NT_ELEM), bytes, dc.stream, dc.mp, K11, K12, K21w, alpha,
                            gamma, At_copy ? Fwork : (void*)em);
         if (At_copy) {
           hipLaunchKernelGGL((convert_kernel<PREC_F64, PREC_F32>), dim3(copy_grid(nF)), dim3(256), 0, dc.stream, Fwork,
@@ -1114,7 +1011,7 @@ hipError_t launch_precond_factor(const DevCtx& dc, const void* K11, const void* 
               hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
           if (err != hipSuccess) return err;
         }
-        hipLaunchKernelGGL(k, dim3((unsigned)dc.E), dim3(NT_ELEM), bytes, dc.stream, dc.ops, dc.mp, K11, K12, alpha,
+        hipLaunchKernelGGL(k, dim3((unsigned)dc.E), dim3(NT_ELEM), bytes, dc.stream, dc.mp, K11, K12, K21w, alpha,
                            gamma, At_copy ? Fwork : (void*)em);
         if (At_copy) {
           hipLaunchKernelGGL((convert_kernel<PREC_F32, PREC_F32>), dim3(copy_grid(nF)), dim3(256), 0, dc.stream, Fwork,

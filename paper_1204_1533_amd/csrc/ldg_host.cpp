@@ -326,7 +326,7 @@ static ldg_status assemble(ldg_ctx c, const double* U, double alpha, double gamm
     const size_t NR = (size_t)dc.NP * dc.M;
     TRY(grow(c, (void**)&c->d_Dense, &c->capDense, sizeof(double) * dc.E * NR * NR));
   }
-  HIPCK(c, launch_precond_factor(dc, c->d_K11, c->d_K12, prec, alpha, gamma, c->d_F, fprec, c->d_Fem,
+  HIPCK(c, launch_precond_factor(dc, c->d_K11, c->d_K12, c->d_K21w, prec, alpha, gamma, c->d_F, fprec, c->d_Fem,
                                  keep ? c->d_At : nullptr, block_lu ? c->d_Dense : nullptr));
   c->assembled_kind = c->precond_kind;
   c->assembled = true;

@@ -134,10 +134,11 @@ hipError_t launch_jacvec(const DevCtx& c, const void* K11, const void* K12, int 
                          const double* x, const double* w, double* y);
 
 // Preconditioner A~ (line pattern) formed from the stored K11/K12 and the
-// K21 weights (node-fastest in Fwork), then factorised by block ILU(0): the
-// factors end in Fem in the apply layout above (precision fprec).
-hipError_t launch_precond_factor(const DevCtx& c, const void* K11, const void* K12, int prec, double alpha,
-                                 double gamma, void* Fwork, int fprec, void* Fem, float* At_copy,
+// stored K21 weights K21w (launch_k21_weights; unused without viscous terms),
+// then factorised by block ILU(0): the factors end in Fem in the apply layout
+// above (precision fprec).
+hipError_t launch_precond_factor(const DevCtx& c, const void* K11, const void* K12, const double* K21w, int prec,
+                                 double alpha, double gamma, void* Fwork, int fprec, void* Fem, float* At_copy,
                                  double* dense = nullptr);
 // exact element-block LU of A~: element-major A~ (FP64 or FP32) -> dense
 // [E][NR][NR] L\U (FP64, unit lower L), NR = Np m <= 768; and its apply
