@@ -7,8 +7,9 @@
 // forward products X W, the input gradients dY W^T and the weight gradients
 // X^T dY.  Workgroup tile 64 x 64 with a 32-deep K step staged in LDS; four
 // wavefronts each own a 32 x 32 sub-tile made of 2 x 2 16 x 16 MFMA tiles:
-//   BF16 operands: v_mfma_f32_16x16x16bf16_1k (lane holds row lane%16,
-//                  k = 4 (lane/16) .. +3),
+//   BF16 operands: v_mfma_f32_16x16x32_bf16 (lane holds row lane%16,
+//                  k = 8 (lane/16) .. +7; the whole 32-deep step in one
+//                  instruction),
 //   FP32 operands: v_mfma_f32_16x16x4f32      (lane holds row lane%16,
 //                  k = lane/16);
 // the 16 x 16 FP32 result puts rows 4 (lane/16) + t, t = 0..3, of column
@@ -21,7 +22,8 @@
 
 namespace ldg {
 
-typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef short short8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
 constexpr int GT_M = 64, GT_N = 64, GT_K = 32;
@@ -59,25 +61,29 @@ __device__ __forceinline__ void mma_tile(const T (*sA)[GT_K + 2], const T (*sB)[
 template <>
 __device__ __forceinline__ void mma_tile<uint16_t>(const uint16_t (*sA)[GT_K + 2], const uint16_t (*sB)[GT_K + 2],
                                                    int wm, int wn, int lane, float4_t (&acc)[2][2]) {
+  static_assert(GT_K == 32, "one 16x16x32 step per staged K tile");
+  const int kq = 8 * (lane >> 4);
+  bf16x8_t a[2], b[2];
 #pragma unroll
-  for (int ks = 0; ks < GT_K; ks += 16) {
-    const int kq = ks + 4 * (lane >> 4);
-    short4_t a[2], b[2];
+  for (int i = 0; i < 2; ++i) {
+    const uint16_t* p = sA[wm + 16 * i + (lane & 15)] + kq;
+    short8_t v;
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const uint16_t* p = sA[wm + 16 * i + (lane & 15)] + kq;
-      a[i] = short4_t{(short)p[0], (short)p[1], (short)p[2], (short)p[3]};
-    }
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const uint16_t* p = sB[wn + 16 * j + (lane & 15)] + kq;
-      b[j] = short4_t{(short)p[0], (short)p[1], (short)p[2], (short)p[3]};
-    }
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+    for (int q = 0; q < 8; ++q) v[q] = (short)p[q];
+    a[i] = __builtin_bit_cast(bf16x8_t, v);
   }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const uint16_t* p = sB[wn + 16 * j + (lane & 15)] + kq;
+    short8_t v;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = (short)p[q];
+    b[j] = __builtin_bit_cast(bf16x8_t, v);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
 }
 
 template <>
