@@ -297,7 +297,9 @@ struct GradLayout {
   static constexpr int NITEM = (NOUT + NT_ELEM - 1) / NT_ELEM;
 };
 
-template <int D, int P, int EQ>
+// C22: the trace carries the C22 jump of the normal viscous flux of Qc (the
+// coupled system); instantiated only where that system is solved
+template <int D, int P, int EQ, bool C22>
 __global__ void __launch_bounds__(NT_ELEM) grad_kernel(LineOps ops, MeshParams mp, const double* __restrict__ U,
                                                        double* __restrict__ Q, int homogeneous,
                                                        const double* __restrict__ Qc) {
@@ -377,8 +379,8 @@ __global__ void __launch_bounds__(NT_ELEM) grad_kernel(LineOps ops, MeshParams m
 #pragma unroll
         for (int c = 0; c < M; ++c) sUh[i * M + c] = U[(nb * M + c) * NP + nd];
       }
-      if constexpr (Eq<D, EQ>::VIS) {
-        if (Qc && (kind == BC_INTERIOR || kind == BC_NEUMANN)) {
+      if constexpr (C22) {
+        if (kind == BC_INTERIOR || kind == BC_NEUMANN) {
           // C22 [[F . nbar]] with the inside as the positive side: interior faces
           // (F_in - F_out) . nbar, Neumann faces F_in . nbar - g_N (nbar the unit outward normal)
           double nbar[D], nn = 0.0;
@@ -479,14 +481,19 @@ hipError_t launch_gradient(const DevCtx& dc, const double* U, double* Q, bool ho
   LDG_DISPATCH(dc, {
     using L = GradLayout<D, P, EQ>;
     static_assert(L::bytes <= LDS_PER_CU, "gradient workspace must fit one CU's LDS");
-    auto kern = grad_kernel<D, P, EQ>;
+    const bool c22 = dc.mp.c22 != 0.0 && Qc;
+    if (c22 && EQ != EQ_POISSON) return hipErrorInvalidValue;
+    auto kern = grad_kernel<D, P, EQ, false>;
+    if constexpr (EQ == EQ_POISSON) {
+      if (c22) kern = grad_kernel<D, P, EQ, true>;
+    }
     if (L::bytes > 65536) {
       hipError_t err = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L::bytes);
       if (err != hipSuccess) return err;
     }
     const int64_t grid = (dc.E + L::EPB - 1) / L::EPB;
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT_ELEM), L::bytes, dc.stream, dc.ops, dc.mp, U, Q,
-                       homogeneous ? 1 : 0, dc.mp.c22 != 0.0 ? Qc : nullptr);
+                       homogeneous ? 1 : 0, c22 ? Qc : nullptr);
     return hipGetLastError();
   })
 }
