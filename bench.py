@@ -76,7 +76,9 @@ def roofline(pr, reps, prec):
     Algorithmic bytes per node (m components, D dimensions, p degree, e bytes per stored entry):
       split product: K11 (Dp+1+2D) m^2 e + K12 (Dp+1+D) m^2 D e + x 8m + w = K21 x 8mD + y 8m
       ILU(0) apply : factors (Dp+1) m^2 e + r 8m + z 8m
-      K21 x        : stored weights (Dp+1+D) D 8 + x 8m + w 8mD
+      K21 x        : stored weights (Dp+1+D) D ew + x 8m + w 8mD, ew = 4 (FP32 copy) in the products
+                     with stored FP32 / BF16 blocks, 8 in the refinement's exact products and with
+                     FP64 storage; the per-launch figure averages the step's launches of both
     """
     import numpy as np
     me = pr.mesh
@@ -86,8 +88,10 @@ def roofline(pr, reps, prec):
     per_node = {
         "jacvec": (D * p + 1 + 2 * D) * m * m * e + (D * p + 1 + D) * m * m * D * e + 8 * m + 8 * m * D + 8 * m,
         "precond_apply": (D * p + 1) * m * m * e + 16 * m,
-        "k21_product": (D * p + 1 + D) * D * 8 + 8 * m + 8 * m * D,
+        "k21_product": None,
     }
+    k21_f64 = (D * p + 1 + D) * D * 8 + 8 * m + 8 * m * D
+    k21_stored = (D * p + 1 + D) * D * (8 if prec == 0 else 4) + 8 * m + 8 * m * D
     keys = {"jacvec": ("t_jacvec_ms", "n_jacvec"), "precond_apply": ("t_precond_ms", "n_precond"),
             "k21_product": ("t_k21_ms", "n_k21")}
     allk = {}
@@ -97,7 +101,11 @@ def roofline(pr, reps, prec):
         if n == 0:
             continue
         avg_ms = tot / n
-        byts = per_node[k] * nodes
+        if k == "k21_product":
+            n_stored = min(n, int(np.sum([r["n_jacvec"] for r in reps])))
+            byts = (n_stored * k21_stored + (n - n_stored) * k21_f64) / n * nodes
+        else:
+            byts = per_node[k] * nodes
         gbs = byts / (avg_ms * 1e-3) / 1e9
         allk[k] = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
                    "traffic": None, "avg_ms": avg_ms, "launches": n, "bytes_per_launch": byts,

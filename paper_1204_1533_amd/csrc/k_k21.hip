@@ -183,8 +183,10 @@ __global__ void __launch_bounds__(NT_ELEM) k21_weights_kernel(LineOps ops_arg, M
   }
 }
 
-template <int D, int P, int EQ>
-__global__ void __launch_bounds__(256) k21_apply_kernel(MeshParams mp, const double* __restrict__ Wt,
+// TW: the stored weights' type (FP64, or the FP32 copy used beside stored
+// low-precision blocks); products accumulate in FP64 either way.
+template <int D, int P, int EQ, class TW>
+__global__ void __launch_bounds__(256) k21_apply_kernel(MeshParams mp, const TW* __restrict__ Wt,
                                                         const double* __restrict__ x, double* __restrict__ w) {
   constexpr int N1 = P + 1, NP = ipow(N1, D), NL = ipow(N1, D - 1), M = Eq<D, EQ>::M, NSL = D * P + 1;
   constexpr int EPB = NP >= 256 ? 1 : 256 / NP;
@@ -209,7 +211,7 @@ __global__ void __launch_bounds__(256) k21_apply_kernel(MeshParams mp, const dou
   for (int s = 0; s < NSL + D; ++s) {
     double wt[D], xv[M];
 #pragma unroll
-    for (int d = 0; d < D; ++d) wt[d] = Wt[((int64_t)s * D + d) * NN + gn];
+    for (int d = 0; d < D; ++d) wt[d] = (double)Wt[((int64_t)s * D + d) * NN + gn];
     if (s < NSL) {
       const int b = slot_col<D, P>(a, s);
 #pragma unroll
@@ -251,14 +253,34 @@ hipError_t launch_k21_weights(const DevCtx& dc, double* Wt) {
   })
 }
 
-hipError_t launch_k21_apply(const DevCtx& dc, const double* Wt, const double* x, double* w) {
+template <class TW>
+static hipError_t k21_apply_any(const DevCtx& dc, const TW* Wt, const double* x, double* w) {
   LDG_DISPATCH(dc, {
     constexpr int NP = ipow(P + 1, D);
     constexpr int EPB = NP >= 256 ? 1 : 256 / NP;
     const unsigned grid = (unsigned)((dc.E + EPB - 1) / EPB);
-    hipLaunchKernelGGL((k21_apply_kernel<D, P, EQ>), dim3(grid), dim3(256), 0, dc.stream, dc.mp, Wt, x, w);
+    hipLaunchKernelGGL((k21_apply_kernel<D, P, EQ, TW>), dim3(grid), dim3(256), 0, dc.stream, dc.mp, Wt, x, w);
     return hipGetLastError();
   })
+}
+
+hipError_t launch_k21_apply(const DevCtx& dc, const double* Wt, const double* x, double* w) {
+  return k21_apply_any(dc, Wt, x, w);
+}
+hipError_t launch_k21_apply_f32(const DevCtx& dc, const float* Wt, const double* x, double* w) {
+  return k21_apply_any(dc, Wt, x, w);
+}
+
+__global__ void __launch_bounds__(256) to_f32_kernel(const double* __restrict__ in, float* __restrict__ out, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (float)in[i];
+}
+hipError_t launch_k21_weights_f32(const DevCtx& dc, const double* Wt, float* Wf) {
+  const int64_t n = (int64_t)(dc.D * dc.P + 1 + dc.D) * dc.D * dc.E * dc.NP;
+  const int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(to_f32_kernel, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, dc.stream, Wt, Wf,
+                     n);
+  return hipGetLastError();
 }
 
 }  // namespace ldg

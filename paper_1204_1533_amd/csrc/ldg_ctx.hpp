@@ -34,6 +34,7 @@ struct ldg_ctx_s {
   double* d_Jwork = nullptr;  // point flux Jacobians of the assembly
   size_t capJwork = 0;
   double* d_K21w = nullptr;  // stored K21 weights [slot][d][E Np], computed on first use
+  float* d_K21f = nullptr;  // FP32 copy of the K21 weights
   // assembled state
   bool assembled = false;
   int assembled_kind = 0;  // preconditioner built by the last assembly

@@ -83,7 +83,7 @@ void ldg_destroy(ldg_ctx c) {
   void* ptrs[] = {c->d_xyz, c->d_face_nbr, c->d_nbr_node, c->d_sw, c->d_gD, c->d_gN, c->d_S, c->d_Q, c->d_W, c->d_W2,
                   c->d_K11, c->d_K12, c->d_F, c->d_Fem, c->d_Ua, c->d_Qa, c->d_V, c->d_Z, c->d_R, c->d_G, c->d_x, c->d_r, c->d_z,
                   c->d_tmp, c->d_Un, c->d_partial, c->d_h, c->d_Uold, c->d_st_Un, c->d_st_comb, c->d_st_K,
-                  c->d_K21w, c->d_Dense, c->d_geo, c->d_Jwork, c->d_cwork};
+                  c->d_K21w, c->d_Dense, c->d_geo, c->d_Jwork, c->d_cwork, c->d_K21f};
   for (void* p : ptrs)
     if (p) hipFree(p);
   learned_free(c);
@@ -295,6 +295,8 @@ static ldg_status assemble(ldg_ctx c, const double* U, double alpha, double gamm
     // first assembly and serve every product after it
     TRY(dev_alloc(c, &c->d_K21w, (size_t)(dc.D * dc.P + 1 + dc.D) * dc.D * c->nnode));
     HIPCK(c, launch_k21_weights(dc, c->d_K21w));
+    TRY(dev_alloc(c, &c->d_K21f, (size_t)(dc.D * dc.P + 1 + dc.D) * dc.D * c->nnode));
+    HIPCK(c, launch_k21_weights_f32(dc, c->d_K21w, c->d_K21f));
   }
   const int fprec = prec;
   const size_t nF = (size_t)nsF * dc.M * dc.M * c->nnode;
@@ -369,7 +371,11 @@ ldg_status apply_op_with(ldg_ctx c, const double* x, double* y, bool exact, doub
   const bool vis = dc.EQ != LDG_EULER;
   if (vis) {
     Span sp(c, 1);
-    if (c->d_K21w)
+    // the stored low-precision operator takes the FP32 weights; FP64 storage and
+    // the exact tangent the FP64 ones
+    if (c->d_K21f && !exact && c->prec != LDG_F64)
+      HIPCK(c, launch_k21_apply_f32(dc, c->d_K21f, x, W));
+    else if (c->d_K21w)
       HIPCK(c, launch_k21_apply(dc, c->d_K21w, x, W));
     else
       HIPCK(c, launch_gradient(dc, x, W, true));

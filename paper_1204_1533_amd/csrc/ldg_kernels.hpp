@@ -119,6 +119,10 @@ hipError_t launch_residual_tangent(const DevCtx& c, const double* U, const doubl
 // computed once from the geometry; w = K21 x with them.
 hipError_t launch_k21_weights(const DevCtx& c, double* Wt);
 hipError_t launch_k21_apply(const DevCtx& c, const double* Wt, const double* x, double* w);
+// FP32 copy of the weights, and the product with it (beside stored FP32 / BF16
+// blocks, whose rounding is far larger)
+hipError_t launch_k21_weights_f32(const DevCtx& c, const double* Wt, float* Wf);
+hipError_t launch_k21_apply_f32(const DevCtx& c, const float* Wt, const double* x, double* w);
 
 // Jacobian blocks; prec: 0 f64, 1 f32, 2 bf16.  Layout [slot][row comp][col comp][E*Np].
 // Jacobian blocks in three launches: geometry record per element (once per

@@ -17,7 +17,8 @@ Bounds (written per check below):
 * Products y = (alpha I - gamma A) x: max |y_gpu - y_orc| <= 1e-14 (|x|_inf + gamma |A|_row |x|_inf)
   with |A|_row the largest absolute row sum of K11 + |K12| |K21| (measured at most 1e-15); for
   stored low-precision blocks the oracle multiplies the GPU's stored values (FP64 accumulation on
-  both sides).
+  both sides), and the GPU's w = K21 x uses FP32 copies of the K21 weights, which adds
+  gamma 2^-24 max(|K12| row sum) max(|K21| row sum) |x|_inf.
 * Preconditioner apply: max |z_gpu - z_orc| <= 1e-13 |z_orc|_inf (measured at most 7e-15; FP64
   factors, or the GPU's stored low-precision factors applied by the oracle).
 * Newton step, per solution component c: both sides reach a linear residual <= 1e-8 (GPU) / 1e-10
@@ -185,8 +186,12 @@ def test_precond_low_precision_factors_apply_and_product(name, prec):
     y = torch.empty(x.shape, dtype=torch.float64, device="cuda")
     ctx.ldg_jacvec(x.cuda(), y, False)
     err = float((y.cpu() - yo).abs().max())
-    record(name, f"split product {prec} (stored blocks)", err, 1e-14 * scale)
-    assert err <= 1e-14 * scale
+    # beside stored low-precision blocks the product takes w = K21 x from FP32 copies of the K21
+    # weights: |dw| <= 2^-24 |K21| |x|, so |dy| <= gamma |K12| 2^-24 |K21| |x| on top of the
+    # FP64 accumulation bound
+    bound = 1e-14 * scale + gamma * 2.0 ** -24 * float(a12) * float(x.abs().max())
+    record(name, f"split product {prec} (stored blocks, FP32 K21 weights)", err, bound)
+    assert err <= bound
     ctx.close()
 
 
