@@ -50,17 +50,6 @@ struct JacShape {
   static constexpr int NS12 = D * P + 1 + D;
 };
 
-// Geometry record of an element: [Ag: D][NLG][D] Gauss-point metric a_n,
-// [Nf: D][NLS][D] outward non-unit normals of the line ends, [Js: NP] -1/J.
-template <int D, int P>
-struct GeoShape {
-  static constexpr int N1 = P + 1, NG = n_gauss(P), NP = ipow(N1, D), NL = ipow(N1, D - 1);
-  static constexpr int oAg = 0;
-  static constexpr int oNf = oAg + D * NL * NG * D;
-  static constexpr int oJs = oNf + D * NL * 2 * D;
-  static constexpr int REC = oJs + NP;
-};
-
 // LDS copy of the 1-D operators (per-lane indexing of a kernel argument would
 // need private copies)
 __device__ __forceinline__ const LineOps& stage_ops(const LineOps& ops_arg, double* dst) {

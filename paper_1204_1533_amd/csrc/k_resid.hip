@@ -1,13 +1,12 @@
 // Residual R = F(U) and LDG gradient Q = D(U) of the line-DG scheme.
 //
-// One workgroup owns EPB elements.  Each element's nodal state, node
-// coordinates and nodal mapping gradient are staged in LDS; every reference
-// line of every direction is then processed from LDS:
+// One workgroup owns EPB elements.  Each element's nodal state is staged in
+// LDS, the geometry (Gauss-point metrics a_n = J G^{-T} N_n of eq. contraflux,
+// exact for the Q_p map, line-end normals and 1/J) is read from the record
+// computed once per context; every reference line of every direction is then
+// processed from LDS:
 //   * Gauss phase (one work item per line and Gauss point): interpolate the
-//     state to the point, evaluate the mapping gradient there exactly (the
-//     derivative along the line from the coordinates, the other columns
-//     interpolated from nodal values), form the non-unit normal
-//     a_n = J G^{-T} N_n (eq. contraflux) and the contravariant flux F . a_n;
+//     state to the point and form the contravariant flux F . a_n;
 //   * face phase (one work item per line end): the point flux at the face
 //     node with the coinciding node of the neighbour (Riemann + LDG switch,
 //     Section 3), or the boundary flux of the face's kind (Dirichlet,
@@ -38,48 +37,9 @@ template <> struct IO<Dual<1>> {
 __device__ __forceinline__ double tangent_or_value(double x) { return x; }
 __device__ __forceinline__ double tangent_or_value(const Dual<1>& x) { return x.d[0]; }
 
-template <int D, int N1>
-__device__ __forceinline__ void nodal_G_item(const double* sX, double* sG, const LineOps& ops, int node, int a, int b,
-                                             int NP) {
-  int s = 1;
-  for (int k = 0; k < b; ++k) s *= N1;
-  const int tb = (node / s) % N1;
-  const int base = node - tb * s;
-  double acc = 0.0;
-#pragma unroll
-  for (int q = 0; q < N1; ++q) acc += ops.Dn[tb][q] * sX[a * NP + base + q * s];
-  sG[(a * D + b) * NP + node] = acc;
-}
-
-// mapping gradient at Gauss point g of line (n, l): exact for the Q_p map
-template <int D, int N1>
-__device__ __forceinline__ void gauss_metric(const double* sX, const double* sG, const LineOps& ops, int n, int l,
-                                             int g, int NP, double* an) {
-  double G[D][D];
-#pragma unroll
-  for (int a = 0; a < D; ++a)
-#pragma unroll
-    for (int b = 0; b < D; ++b) {
-      double acc = 0.0;
-      if (b == n) {
-#pragma unroll
-        for (int t = 0; t < N1; ++t) acc += ops.Dg[g][t] * sX[a * NP + line_node<D, N1>(n, l, t)];
-      } else {
-#pragma unroll
-        for (int t = 0; t < N1; ++t) acc += ops.I[g][t] * sG[(a * D + b) * NP + line_node<D, N1>(n, l, t)];
-      }
-      G[a][b] = acc;
-    }
-  cofactor_row<D>(G, n, an);
-}
-
-template <int D>
-__device__ __forceinline__ void node_G(const double* sG, int node, int NP, double G[D][D]) {
-#pragma unroll
-  for (int a = 0; a < D; ++a)
-#pragma unroll
-    for (int b = 0; b < D; ++b) G[a][b] = sG[(a * D + b) * NP + node];
-}
+// Geometry (Gauss-point metrics a_n, line-end normals, -1/J) comes from the
+// per-element record computed once per context from the node coordinates
+// (GeoShape, geometry_kernel).
 
 // --------------------------------------------------------------------------- residual
 // Same organisation as the gradient kernel below: directions one after
@@ -99,9 +59,7 @@ struct ResidLayout {
   static constexpr size_t oF = oQ + sizeof(T) * EPB * QW * NP;
   static constexpr size_t oH = oF + sizeof(T) * EPB * NL * NG * M;
   static constexpr size_t oW = oH + sizeof(T) * EPB * NL * 2 * M;
-  static constexpr size_t oX = oW + sizeof(T) * EPB * NL * NG * NW;
-  static constexpr size_t oG = oX + sizeof(double) * EPB * D * NP;
-  static constexpr size_t oJ = oG + sizeof(double) * EPB * D * D * NP;
+  static constexpr size_t oJ = oW + sizeof(T) * EPB * NL * NG * NW;
   static constexpr size_t oA = oJ + sizeof(double) * EPB * NP;
   static constexpr size_t bytes = oA + sizeof(double) * EPB * NL * NG * D;
   static constexpr int NITEM = (EPB * M * NP + NT_ELEM - 1) / NT_ELEM;
@@ -112,6 +70,7 @@ __global__ void __launch_bounds__(NT_ELEM) resid_kernel(LineOps ops, MeshParams 
                                                         const double* __restrict__ Ut, const double* __restrict__ Q,
                                                         const double* __restrict__ Qt, double* __restrict__ R) {
   using L = ResidLayout<D, P, EQ, T>;
+  using GR = GeoShape<D, P>;
   constexpr int N1 = L::N1, NG = L::NG, NP = L::NP, NL = L::NL, M = L::M, EPB = L::EPB, QW = L::QW;
   constexpr bool INV = Eq<D, EQ>::INV, VIS = Eq<D, EQ>::VIS;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -119,8 +78,6 @@ __global__ void __launch_bounds__(NT_ELEM) resid_kernel(LineOps ops, MeshParams 
   T* sQ = reinterpret_cast<T*>(smem_raw + L::oQ);
   T* sF = reinterpret_cast<T*>(smem_raw + L::oF);
   T* sH = reinterpret_cast<T*>(smem_raw + L::oH);
-  double* sX = reinterpret_cast<double*>(smem_raw + L::oX);
-  double* sG = reinterpret_cast<double*>(smem_raw + L::oG);
   double* sJ = reinterpret_cast<double*>(smem_raw + L::oJ);
   T* sWg = reinterpret_cast<T*>(smem_raw + L::oW);
   double* sAg = reinterpret_cast<double*>(smem_raw + L::oA);
@@ -133,19 +90,9 @@ __global__ void __launch_bounds__(NT_ELEM) resid_kernel(LineOps ops, MeshParams 
   for (int i = tid; i < ne * M * NP; i += NT_ELEM) sU[i] = IO<T>::load(U, Ut, e0 * M * NP + i);
   if constexpr (VIS)
     for (int i = tid; i < ne * QW * NP; i += NT_ELEM) sQ[i] = IO<T>::load(Q, Qt, e0 * QW * NP + i);
-  for (int i = tid; i < ne * D * NP; i += NT_ELEM) sX[i] = mp.xyz[e0 * D * NP + i];
+  // -1/J of the nodes from the geometry record
+  for (int i = tid; i < ne * NP; i += NT_ELEM) sJ[i] = mp.geo[(e0 + i / NP) * GR::REC + GR::oJs + i % NP];
   __syncthreads();
-  for (int i = tid; i < ne * D * D * NP; i += NT_ELEM) {
-    const int e = i / (D * D * NP), r = i % (D * D * NP);
-    const int ab = r / NP, node = r % NP;
-    nodal_G_item<D, N1>(sX + e * D * NP, sG + e * D * D * NP, ops, node, ab / D, ab % D, NP);
-  }
-  __syncthreads();
-  for (int i = tid; i < ne * NP; i += NT_ELEM) {
-    double G[D][D];
-    node_G<D>(sG + (i / NP) * D * D * NP, i % NP, NP, G);
-    sJ[i] = -1.0 / det<D>(G);
-  }
   T acc[L::NITEM];
 #pragma unroll
   for (int q = 0; q < L::NITEM; ++q) acc[q] = cst<T>(0.0);
@@ -163,11 +110,9 @@ __global__ void __launch_bounds__(NT_ELEM) resid_kernel(LineOps ops, MeshParams 
       sWg[i] = a;
     }
     for (int i = tid; i < ne * NL * NG; i += NT_ELEM) {
-      const int e = i / (NL * NG), l = (i / NG) % NL, g = i % NG;
-      double an[D];
-      gauss_metric<D, N1>(sX + e * D * NP, sG + e * D * D * NP, ops, n, l, g, NP, an);
+      const int e = i / (NL * NG), lg = i % (NL * NG);
 #pragma unroll
-      for (int d = 0; d < D; ++d) sAg[i * D + d] = an[d];
+      for (int d = 0; d < D; ++d) sAg[i * D + d] = mp.geo[(e0 + e) * GR::REC + GR::oAg + (n * NL * NG + lg) * D + d];
     }
     __syncthreads();
     // Gauss phase: contravariant flux F . a_n at every Gauss point of the direction-n lines
@@ -197,11 +142,9 @@ __global__ void __launch_bounds__(NT_ELEM) resid_kernel(LineOps ops, MeshParams 
       const int e = i / (NL * 2), l = (i / 2) % NL, s = i % 2;
       const int64_t eg = e0 + e;
       const int nin = line_node<D, N1>(n, l, s ? P : 0);
-      double G[D][D], an[D], nrm[D];
-      node_G<D>(sG + e * D * D * NP, nin, NP, G);
-      cofactor_row<D>(G, n, an);
+      double nrm[D];  // outward non-unit normal of the line end
 #pragma unroll
-      for (int d = 0; d < D; ++d) nrm[d] = s ? an[d] : -an[d];
+      for (int d = 0; d < D; ++d) nrm[d] = mp.geo[eg * GR::REC + GR::oNf + (n * NL * 2 + l * 2 + s) * D + d];
       const int f = 2 * n + s;
       const int64_t nb = mp.face_nbr[eg * 2 * D + f];
       const int kind = face_kind(nb);
@@ -284,9 +227,7 @@ struct GradLayout {
   static constexpr int M = Eq<D, EQ>::M;
   static constexpr int EPB = elems_per_block(NP, M);
   static constexpr int oU = 0;
-  static constexpr int oX = oU + EPB * M * NP;
-  static constexpr int oG = oX + EPB * D * NP;
-  static constexpr int oJ = oG + EPB * D * D * NP;
+  static constexpr int oJ = oU + EPB * M * NP;
   static constexpr int oUg = oJ + EPB * NP;
   static constexpr int oAg = oUg + EPB * NL * NG * M;
   static constexpr int oUh = oAg + EPB * NL * NG * D;
@@ -304,12 +245,11 @@ __global__ void __launch_bounds__(NT_ELEM) grad_kernel(LineOps ops, MeshParams m
                                                        double* __restrict__ Q, int homogeneous,
                                                        const double* __restrict__ Qc) {
   using L = GradLayout<D, P, EQ>;
+  using GR = GeoShape<D, P>;
   constexpr int N1 = L::N1, NG = L::NG, NP = L::NP, NL = L::NL, M = L::M, EPB = L::EPB;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* sm = reinterpret_cast<double*>(smem_raw);
   double* sU = sm + L::oU;
-  double* sX = sm + L::oX;
-  double* sG = sm + L::oG;
   double* sJ = sm + L::oJ;
   double* sUg = sm + L::oUg;
   double* sAg = sm + L::oAg;
@@ -320,19 +260,9 @@ __global__ void __launch_bounds__(NT_ELEM) grad_kernel(LineOps ops, MeshParams m
   const int ne = (int)min((int64_t)EPB, mp.E - e0);
   const int tid = threadIdx.x;
   for (int i = tid; i < ne * M * NP; i += NT_ELEM) sU[i] = U[e0 * M * NP + i];
-  for (int i = tid; i < ne * D * NP; i += NT_ELEM) sX[i] = mp.xyz[e0 * D * NP + i];
+  // 1/J of the nodes (the record holds -1/J)
+  for (int i = tid; i < ne * NP; i += NT_ELEM) sJ[i] = -mp.geo[(e0 + i / NP) * GR::REC + GR::oJs + i % NP];
   __syncthreads();
-  for (int i = tid; i < ne * D * D * NP; i += NT_ELEM) {
-    const int e = i / (D * D * NP), r = i % (D * D * NP);
-    const int ab = r / NP, node = r % NP;
-    nodal_G_item<D, N1>(sX + e * D * NP, sG + e * D * D * NP, ops, node, ab / D, ab % D, NP);
-  }
-  __syncthreads();
-  for (int i = tid; i < ne * NP; i += NT_ELEM) {
-    double G[D][D];
-    node_G<D>(sG + (i / NP) * D * D * NP, i % NP, NP, G);
-    sJ[i] = 1.0 / det<D>(G);
-  }
   double acc[L::NITEM];
 #pragma unroll
   for (int q = 0; q < L::NITEM; ++q) acc[q] = 0.0;
@@ -340,10 +270,9 @@ __global__ void __launch_bounds__(NT_ELEM) grad_kernel(LineOps ops, MeshParams m
   for (int n = 0; n < D; ++n) {
     for (int i = tid; i < ne * NL * NG; i += NT_ELEM) {
       const int e = i / (NL * NG), l = (i / NG) % NL, g = i % NG;
-      double an[D];
-      gauss_metric<D, N1>(sX + e * D * NP, sG + e * D * D * NP, ops, n, l, g, NP, an);
 #pragma unroll
-      for (int d = 0; d < D; ++d) sAg[i * D + d] = an[d];
+      for (int d = 0; d < D; ++d)
+        sAg[i * D + d] = mp.geo[(e0 + e) * GR::REC + GR::oAg + (n * NL * NG + l * NG + g) * D + d];
 #pragma unroll
       for (int c = 0; c < M; ++c) {
         double a = 0.0;
@@ -356,11 +285,8 @@ __global__ void __launch_bounds__(NT_ELEM) grad_kernel(LineOps ops, MeshParams m
       const int e = i / (NL * 2), l = (i / 2) % NL, s = i % 2;
       const int64_t eg = e0 + e;
       const int nin = line_node<D, N1>(n, l, s ? P : 0);
-      double G[D][D], an[D];
-      node_G<D>(sG + e * D * D * NP, nin, NP, G);
-      cofactor_row<D>(G, n, an);
 #pragma unroll
-      for (int d = 0; d < D; ++d) sNh[i * D + d] = s ? an[d] : -an[d];
+      for (int d = 0; d < D; ++d) sNh[i * D + d] = mp.geo[eg * GR::REC + GR::oNf + (n * NL * 2 + l * 2 + s) * D + d];
       const int f = 2 * n + s;
       const int64_t nb = mp.face_nbr[eg * 2 * D + f];
       const int kind = face_kind(nb);

@@ -54,6 +54,7 @@ struct MeshParams {
   const double* gN;        // [E][2D][m][Nf] or null
   const double* S;         // [E][m][Np] or null
   double c22;              // LDG C22 (eqs. ldgflux2, neumann2); 0: the reduced system
+  const double* geo;       // per-element geometry record (GeoShape), fixed by the mesh
 };
 
 // Kind of a face from its face_nbr entry: a neighbour (interior) or a boundary

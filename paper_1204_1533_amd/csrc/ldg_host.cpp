@@ -217,6 +217,12 @@ ldg_status ldg_create(const ldg_problem_desc* d, void* stream, ldg_ctx* out) {
   mp.gN = nullptr;
   mp.S = nullptr;
   mp.c22 = 0.0;
+  // Gauss-point metrics, line-end normals and -1/J: fixed by the mesh, read by
+  // the residual, gradient and Jacobian kernels
+  if (dev_alloc(c, &c->d_geo, jacobian_geometry_doubles(dc)) != LDG_OK)
+    return bad(LDG_E_NOMEM, "device allocation of the geometry record");
+  if (launch_jacobian_geometry(dc, c->d_geo) != hipSuccess) return bad(LDG_E_HIP, "geometry record");
+  mp.geo = c->d_geo;
   *out = c;
   return LDG_OK;
 }

@@ -21,6 +21,17 @@ struct DevCtx {
 constexpr int NT_ELEM = 256;
 constexpr size_t LDS_PER_CU = 160 * 1024;  // bytes of LDS one workgroup may use on gfx950
 
+// Geometry record of an element: [Ag: D][NLG][D] Gauss-point metric a_n,
+// [Nf: D][NLS][D] outward non-unit normals of the line ends, [Js: NP] -1/J.
+template <int D, int P>
+struct GeoShape {
+  static constexpr int N1 = P + 1, NG = n_gauss(P), NP = ipow(N1, D), NL = ipow(N1, D - 1);
+  static constexpr int oAg = 0;
+  static constexpr int oNf = oAg + D * NL * NG * D;
+  static constexpr int oJs = oNf + D * NL * 2 * D;
+  static constexpr int REC = oJs + NP;
+};
+
 // Elements per workgroup for the residual-type kernels: small 2-D elements
 // are packed so that one workgroup still has several hundred work items.
 __host__ __device__ constexpr int elems_per_block(int NP, int M) {
