@@ -148,10 +148,12 @@ ldg_status ldg_jacobian_assemble(ldg_ctx ctx, const double* U_dev, double alpha,
                                  int32_t storage_prec);
 
 /* y = (alpha I - gamma A) x with the split product of eq. matvecsplit:
- * alpha x - gamma (K11 x + K12 (K21 x)), K21 x computed matrix-free.  With
- * exact_fp64 != 0, A x is the exact FP64 tangent of the residual at the
- * assembled state (forward-mode differentiation), independent of the stored
- * precision.  x_dev, y_dev [E][m][Np], must not alias.
+ * alpha x - gamma (K11 x + K12 (K21 x)), K21 x from the stored per-node K21
+ * weights (FP64; an FP32 copy of them beside FP32 / BF16 storage), FP64
+ * accumulation.  With exact_fp64 != 0, A x is the exact FP64 tangent of the
+ * residual at the assembled state (forward-mode differentiation, FP64 K21
+ * weights), independent of the stored precision.  x_dev, y_dev [E][m][Np],
+ * must not alias.
  * Error: LDG_E_NOT_ASSEMBLED. */
 ldg_status ldg_jacvec(ldg_ctx ctx, const double* x_dev, double* y_dev, int32_t exact_fp64);
 
