@@ -178,3 +178,26 @@ def test_coupled_argument_errors():
         ns.ldg_set_c22(0.05)
     ns.ldg_set_c22(0.0)
     ns.close()
+
+
+def test_coupled_c22_improves_q_rates():
+    """Section 5.1 (Table poitab1) on the GPU: C11 = C22 = 1/20 gives a smaller q error and a higher
+    q convergence rate than C11 = C22 = 0 (perturbed quads, p = 1, 8^2 -> 16^2 -> 32^2; the oracle
+    pins the same comparison at 8^2 and 16^2)."""
+    print("[gpu] coupled q rates", flush=True)
+    err = {}
+    for c in (0.0, 1 / 20):
+        for n in (8, 16, 32):
+            mesh = quad_mesh(n, n, 1, box=((0, 1), (0, 1)), perturb=0.25, seed=3)
+            u, f, g = fields.poisson_sine(mesh)
+            pr = configs.Problem(f"rates{n}", mesh, EQ_POISSON, 1, 0 * u, c11_interior=c, source=f,
+                                 gD=fields.face_values(mesh, u))
+            Ug, Qg, rep = gpu_coupled(pr, c, 1e-11)
+            err[c, n] = float(np.abs(Qg.numpy() - g).max())
+    r0 = [np.log2(err[0.0, n] / err[0.0, 2 * n]) for n in (8, 16)]
+    r1 = [np.log2(err[1 / 20, n] / err[1 / 20, 2 * n]) for n in (8, 16)]
+    print(f"  |q - grad u| C=0: {[err[0.0, n] for n in (8, 16, 32)]}, rates {r0}", flush=True)
+    print(f"  |q - grad u| C=1/20: {[err[1 / 20, n] for n in (8, 16, 32)]}, rates {r1}", flush=True)
+    record("rates_p1", "q error ratio C22=1/20 / C22=0 at 32^2", err[1 / 20, 32] / err[0.0, 32], 0.75)
+    assert err[1 / 20, 32] < 0.75 * err[0.0, 32]
+    assert r1[0] > r0[0] + 0.2 and r1[1] > r0[1]
