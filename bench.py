@@ -340,8 +340,9 @@ def dirk3_reuse_c3(Context):
 
 def euler_residual_bandwidth(Context):
     """FP64 Euler residual on the tiled vortex, 512^2 perturbed quads at p=4 (26.2 M unknowns):
-    median time of 20 evaluations against the HBM roof of its algorithmic bytes (state and node
-    coordinates read, residual written: 8m + 8D + 8m per node) and the FP64 roof."""
+    median time of 20 evaluations against the HBM roof of its algorithmic bytes (state read,
+    residual written: 8m + 8m per node, plus each element's geometry record of
+    D NL NG D + D 2NL D + Np doubles) and the FP64 roof."""
     import numpy as np
     import torch
     from ldg_workloads import configs
@@ -362,13 +363,70 @@ def euler_residual_bandwidth(Context):
         ts.append(a.elapsed_time(b))
     ms = float(np.median(ts))
     nodes = pr.mesh.n_elem * pr.mesh.np_
-    byts = nodes * (8 * pr.m + 8 * pr.mesh.dim + 8 * pr.m)
+    D, n1 = pr.mesh.dim, pr.mesh.p + 1
+    ng = (3 * pr.mesh.p + 2) // 2  # Gauss points per line: ceil((3p + 1) / 2)
+    nl = n1 ** (D - 1)
+    rec = D * nl * ng * D + D * 2 * nl * D + pr.mesh.np_
+    byts = nodes * (8 * pr.m + 8 * pr.m) + pr.mesh.n_elem * rec * 8
     gbs = byts / (ms * 1e-3) / 1e9
     ctx.close()
     log(f"[bench] 512^2 Euler residual: {ms:.3f} ms, {gbs:.0f} GB/s algorithmic")
     return {"workload": f"{pr.name}: {pr.n_dof} unknowns", "ms_per_residual": ms,
             "dof_per_s": pr.n_dof / (ms * 1e-3), "bytes_per_eval": byts, "achieved_gbs": gbs,
             "frac_hbm": gbs / HBM_PEAK_GBS}
+
+
+def coupled_poisson(Context):
+    """Steady coupled (U, Q) solve with C11 = C22 = 1/20 (Section 4.1; the scheme of Table poitab1's
+    second block) on 16^2 perturbed quads, p = 3, next to the reduced system (C22 = 0) solved by one
+    steady Newton step: wall time, outer and inner iterations.  Steady elliptic solves with the
+    element-local preconditioner need iteration counts that grow with the mesh (no global
+    coarse correction; the paper solves these systems with a sparse direct solver), which keeps
+    this measurement small."""
+    import time
+    import torch
+    from ldg_workloads import configs, fields, quad_mesh
+    mesh = quad_mesh(16, 16, 3, box=((0, 1), (0, 1)), perturb=0.2, seed=2)
+    u, f, g = fields.poisson_sine(mesh)
+    pr = configs.Problem("poisson16p3_pert", mesh, configs.EQ_POISSON, 1, 0 * u, c11_interior=1 / 20, source=f,
+                         gD=fields.face_values(mesh, u))
+    ctx = Context(pr.mesh, pr.equation, c11_interior=pr.c11_interior, c11_dirichlet=pr.c11_dirichlet,
+                  stream=torch.cuda.current_stream().cuda_stream)
+    S = torch.as_tensor(pr.source, device="cuda").contiguous()
+    gD = torch.as_tensor(pr.gD, device="cuda").contiguous()
+    ctx.ldg_set_source(S)
+    ctx.ldg_set_dirichlet(gD)
+    E, Np = mesh.n_elem, mesh.np_
+    U = torch.zeros(E, 1, Np, dtype=torch.float64, device="cuda")
+    Q = torch.zeros(E, 1, 2, Np, dtype=torch.float64, device="cuda")
+    out = {"workload": f"{pr.name}: {E * Np} + {2 * E * Np} unknowns (U, Q), C11 = C22 = 1/20"}
+    ctx.ldg_set_c22(1 / 20)
+    kw = dict(rtol=1e-10, inner_rtol=1e-3, restart=60, max_iters=500, raise_on_error=False)
+    ctx.ldg_coupled_solve(U, Q, **kw)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = ctx.ldg_coupled_solve(U, Q, **kw)
+    torch.cuda.synchronize()
+    out["coupled"] = {"ms": 1e3 * (time.perf_counter() - t0), "status": r["status"], "outer_iters": r["iters"],
+                      "inner_iters": r["inner_iters"], "relres": r["relres"],
+                      "q_err_max": float((Q.cpu() - torch.as_tensor(g)).abs().max())}
+    ctx.ldg_set_c22(0.0)
+    U.zero_()
+    ctx.ldg_newton_step(U, U.clone(), 0.0, 1.0, restart=60, max_iters=3000, rtol=1e-10, raise_on_error=False)
+    U.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rr = ctx.ldg_newton_step(U, U.clone(), 0.0, 1.0, restart=60, max_iters=3000, rtol=1e-10, raise_on_error=False)
+    torch.cuda.synchronize()
+    ctx.ldg_gradient(U, Q)
+    torch.cuda.synchronize()
+    out["reduced_c22_0"] = {"ms": 1e3 * (time.perf_counter() - t0), "gmres_iters": rr["gmres_iters"],
+                            "lin_relres": rr["lin_relres"],
+                            "q_err_max": float((Q.cpu() - torch.as_tensor(g)).abs().max())}
+    ctx.close()
+    log(f"[bench] coupled C22 solve: {out['coupled']['ms']:.1f} ms ({r['iters']} outer, {r['inner_iters']} inner); "
+        f"reduced {out['reduced_c22_0']['ms']:.1f} ms")
+    return out
 
 
 def log(msg):
@@ -449,7 +507,7 @@ def main():
     extra = None
     if not args.no_extra:
         extra = {"c3_newton": c3_newton(Context), "dirk3_c3": dirk3_reuse_c3(Context),
-                 "euler_residual_512": euler_residual_bandwidth(Context)}
+                 "euler_residual_512": euler_residual_bandwidth(Context), "coupled_c22": coupled_poisson(Context)}
     last = reps[-1]
     roof = roofline(pr, reps, chosen_prec)
     # residual (gradient + residual kernels) against the FP64 roof with algorithmic operations:
