@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=256, help="elements timed on the CPU oracle")
     ap.add_argument("--no-rk4", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the 16^3, DIRK3 and 512^2 measurements")
+    ap.add_argument("--coupled-only", action="store_true",
+                    help="run only the coupled C22 solve measurement and print its record (for profiling)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="copy 1 GiB between two device buffers first (a reference kernel for profiler counters)")
     return ap.parse_args()
@@ -446,6 +448,9 @@ def main():
     from paper_1204_1533_amd import Context, LDG_BF16, LDG_F64, LDG_F32
 
     torch.cuda.set_device(0)
+    if args.coupled_only:
+        print(json.dumps({"coupled_c22": coupled_poisson(Context)}))
+        return
     if args.calib_copy:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)

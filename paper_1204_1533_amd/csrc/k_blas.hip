@@ -1,7 +1,7 @@
 // FP64 vector kernels for the Krylov solver and the explicit Runge-Kutta loop.
 //
 // multidot : h_j = <V_j, w> for j < k (block partial sums, then a second pass);
-//            the basis vectors are read in tiles of 8 so w is re-read k/8 times.
+//            one block row per tile of 8 basis vectors, so w is read k/8 times.
 // update   : w -= sum_j h_j V_j   (classical Gram-Schmidt projection)
 // lincomb  : y += sum_j c_j V_j   (GMRES solution update)
 #include "ldg_kernels.hpp"
@@ -14,32 +14,31 @@ constexpr int DOT_TILE = 8;
 __global__ void __launch_bounds__(NT_BLAS) multidot_kernel(const double* __restrict__ V, int64_t ldv, int k,
                                                           const double* __restrict__ w, int64_t n,
                                                           double* __restrict__ partial) {
+  // grid: x over row blocks, y over tiles of DOT_TILE basis vectors
   __shared__ double red[NT_BLAS / 64][DOT_TILE];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  for (int j0 = 0; j0 < k; j0 += DOT_TILE) {
-    const int nt = min(DOT_TILE, k - j0);
-    double acc[DOT_TILE];
+  const int j0 = blockIdx.y * DOT_TILE;
+  const int nt = min(DOT_TILE, k - j0);
+  double acc[DOT_TILE];
 #pragma unroll
-    for (int t = 0; t < DOT_TILE; ++t) acc[t] = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * NT_BLAS + tid; i < n; i += (int64_t)gridDim.x * NT_BLAS) {
-      const double wi = w[i];
+  for (int t = 0; t < DOT_TILE; ++t) acc[t] = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * NT_BLAS + tid; i < n; i += (int64_t)gridDim.x * NT_BLAS) {
+    const double wi = w[i];
 #pragma unroll
-      for (int t = 0; t < DOT_TILE; ++t)
-        if (t < nt) acc[t] += V[(int64_t)(j0 + t) * ldv + i] * wi;
-    }
+    for (int t = 0; t < DOT_TILE; ++t)
+      if (t < nt) acc[t] += V[(int64_t)(j0 + t) * ldv + i] * wi;
+  }
 #pragma unroll
-    for (int t = 0; t < DOT_TILE; ++t) {
-      double v = acc[t];
-      for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-      if (lane == 0) red[wid][t] = v;
-    }
-    __syncthreads();
-    if (tid < nt) {
-      double s = 0.0;
-      for (int q = 0; q < NT_BLAS / 64; ++q) s += red[q][tid];
-      partial[(int64_t)blockIdx.x * k + j0 + tid] = s;
-    }
-    __syncthreads();
+  for (int t = 0; t < DOT_TILE; ++t) {
+    double v = acc[t];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) red[wid][t] = v;
+  }
+  __syncthreads();
+  if (tid < nt) {
+    double s = 0.0;
+    for (int q = 0; q < NT_BLAS / 64; ++q) s += red[q][tid];
+    partial[(int64_t)blockIdx.x * k + j0 + tid] = s;
   }
 }
 
@@ -101,7 +100,9 @@ static unsigned grid_for(int64_t n, int nt) {
 hipError_t launch_multidot(const double* V, int64_t ldv, int k, const double* w, int64_t n, double* partial,
                            int nblocks, hipStream_t s) {
   if (k > 128) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(multidot_kernel, dim3(nblocks), dim3(NT_BLAS), 0, s, V, ldv, k, w, n, partial);
+  if (k < 1) return hipSuccess;
+  hipLaunchKernelGGL(multidot_kernel, dim3(nblocks, (k + DOT_TILE - 1) / DOT_TILE), dim3(NT_BLAS), 0, s, V, ldv, k, w,
+                     n, partial);
   return hipGetLastError();
 }
 

@@ -438,8 +438,11 @@ ldg_status ldg_export_operators(ldg_ctx c, double* K11, double* K12, double* F) 
 // V_j . w for j < k (columns of length n, stored one after another), to the host
 static ldg_status dots(ldg_ctx c, int64_t n, const double* V, int k, const double* w, double* host_out) {
   const DevCtx& dc = c->dc;
-  HIPCK(c, launch_multidot(V, n, k, w, n, c->d_partial, c->nblk_dot, dc.stream));
-  HIPCK(c, launch_multidot_finish(c->d_partial, c->nblk_dot, k, c->d_h, dc.stream));
+  // one block per 1024 entries (four per thread), at most nblk_dot: small systems
+  // then reduce over a few blocks instead of many nearly empty ones
+  const int nb = (int)std::min<int64_t>(c->nblk_dot, std::max<int64_t>(1, (n + 1023) / 1024));
+  HIPCK(c, launch_multidot(V, n, k, w, n, c->d_partial, nb, dc.stream));
+  HIPCK(c, launch_multidot_finish(c->d_partial, nb, k, c->d_h, dc.stream));
   HIPCK(c, hipMemcpyAsync(host_out, c->d_h, sizeof(double) * k, hipMemcpyDeviceToHost, dc.stream));
   HIPCK(c, hipStreamSynchronize(dc.stream));
   return LDG_OK;
