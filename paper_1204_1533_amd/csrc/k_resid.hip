@@ -17,8 +17,10 @@
 //     the D lines through the node and scaled by -1/J (eq. semidisc).
 // The only global reads besides the element's own contiguous block are one
 // neighbour node per line end.
-#include "ldg_kernels.hpp"
+#include <type_traits>
+
 #include "ldg_dispatch.hpp"
+#include "ldg_kernels.hpp"
 
 namespace ldg {
 
@@ -58,10 +60,15 @@ struct ResidLayout {
   static constexpr int NW = M + QW;  // state and gradient components interpolated to a Gauss point
   static constexpr size_t oF = oQ + sizeof(T) * EPB * QW * NP;
   static constexpr size_t oH = oF + sizeof(T) * EPB * NL * NG * M;
+  // The dual-number (tangent) variant stages the Gauss-point interpolants and
+  // metrics of a direction in LDS in a phase of their own; the FP64 residual
+  // interpolates inside its Gauss phase (fewer barriers; measured faster for
+  // FP64 and slower for the dual numbers, whose registers it then exhausts).
+  static constexpr bool STAGE = !std::is_same<T, double>::value;
   static constexpr size_t oW = oH + sizeof(T) * EPB * NL * 2 * M;
-  static constexpr size_t oJ = oW + sizeof(T) * EPB * NL * NG * NW;
+  static constexpr size_t oJ = oW + (STAGE ? sizeof(T) * EPB * NL * NG * NW : 0);
   static constexpr size_t oA = oJ + sizeof(double) * EPB * NP;
-  static constexpr size_t bytes = oA + sizeof(double) * EPB * NL * NG * D;
+  static constexpr size_t bytes = oA + (STAGE ? sizeof(double) * EPB * NL * NG * D : 0);
   static constexpr int NITEM = (EPB * M * NP + NT_ELEM - 1) / NT_ELEM;
 };
 
@@ -99,43 +106,80 @@ __global__ void __launch_bounds__(NT_ELEM) resid_kernel(LineOps ops, MeshParams 
 
 #pragma unroll
   for (int n = 0; n < D; ++n) {
-    // interpolation phase: state, gradient and non-unit normal a_n at every Gauss point
-    for (int i = tid; i < ne * NL * NG * NW; i += NT_ELEM) {
-      const int k = i % NW, pt = i / NW;
-      const int e = pt / (NL * NG), l = (pt / NG) % NL, g = pt % NG;
-      const T* src = k < M ? sU + (e * M + k) * NP : sQ + (e * QW + (k - M)) * NP;
-      T a = cst<T>(0.0);
+    if constexpr (L::STAGE) {
+      // interpolation phase: state, gradient and non-unit normal a_n at every Gauss point
+      for (int i = tid; i < ne * NL * NG * NW; i += NT_ELEM) {
+        const int k = i % NW, pt = i / NW;
+        const int e = pt / (NL * NG), l = (pt / NG) % NL, g = pt % NG;
+        const T* src = k < M ? sU + (e * M + k) * NP : sQ + (e * QW + (k - M)) * NP;
+        T a = cst<T>(0.0);
 #pragma unroll
-      for (int t = 0; t < N1; ++t) a += ops.I[g][t] * src[line_node<D, N1>(n, l, t)];
-      sWg[i] = a;
-    }
-    for (int i = tid; i < ne * NL * NG; i += NT_ELEM) {
-      const int e = i / (NL * NG), lg = i % (NL * NG);
-#pragma unroll
-      for (int d = 0; d < D; ++d) sAg[i * D + d] = mp.geo[(e0 + e) * GR::REC + GR::oAg + (n * NL * NG + lg) * D + d];
-    }
-    __syncthreads();
-    // Gauss phase: contravariant flux F . a_n at every Gauss point of the direction-n lines
-    for (int i = tid; i < ne * NL * NG; i += NT_ELEM) {
-      double an[D];
-#pragma unroll
-      for (int d = 0; d < D; ++d) an[d] = sAg[i * D + d];
-      const T* w = sWg + i * NW;
-      T ug[M];
-#pragma unroll
-      for (int c = 0; c < M; ++c) ug[c] = w[c];
-      T f[M];
-#pragma unroll
-      for (int c = 0; c < M; ++c) f[c] = cst<T>(0.0);
-      if constexpr (INV) euler_flux_dot<D, T>(ug, an, mp.gamma, f);
-      if constexpr (VIS) {
-        T qg[M * D];
-#pragma unroll
-        for (int c = 0; c < M * D; ++c) qg[c] = w[M + c];
-        visc_flux_dot_add<D, EQ, T>(ug, qg, an, mp.gamma, mp.mu, mp.prandtl, f);
+        for (int t = 0; t < N1; ++t) a += ops.I[g][t] * src[line_node<D, N1>(n, l, t)];
+        sWg[i] = a;
       }
+      for (int i = tid; i < ne * NL * NG; i += NT_ELEM) {
+        const int e = i / (NL * NG), lg = i % (NL * NG);
 #pragma unroll
-      for (int c = 0; c < M; ++c) sF[i * M + c] = f[c];
+        for (int d = 0; d < D; ++d) sAg[i * D + d] = mp.geo[(e0 + e) * GR::REC + GR::oAg + (n * NL * NG + lg) * D + d];
+      }
+      __syncthreads();
+      // Gauss phase: contravariant flux F . a_n at every Gauss point of the direction-n lines
+      for (int i = tid; i < ne * NL * NG; i += NT_ELEM) {
+        double an[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) an[d] = sAg[i * D + d];
+        const T* w = sWg + i * NW;
+        T ug[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) ug[c] = w[c];
+        T f[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) f[c] = cst<T>(0.0);
+        if constexpr (INV) euler_flux_dot<D, T>(ug, an, mp.gamma, f);
+        if constexpr (VIS) {
+          T qg[M * D];
+#pragma unroll
+          for (int c = 0; c < M * D; ++c) qg[c] = w[M + c];
+          visc_flux_dot_add<D, EQ, T>(ug, qg, an, mp.gamma, mp.mu, mp.prandtl, f);
+        }
+#pragma unroll
+        for (int c = 0; c < M; ++c) sF[i * M + c] = f[c];
+      }
+    } else {
+      // Gauss phase: state and gradient interpolated to the point, the non-unit
+      // normal a_n from the geometry record, and the contravariant flux F . a_n
+      for (int i = tid; i < ne * NL * NG; i += NT_ELEM) {
+        const int e = i / (NL * NG), l = (i / NG) % NL, g = i % NG;
+        double an[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+          an[d] = mp.geo[(e0 + e) * GR::REC + GR::oAg + (n * NL * NG + l * NG + g) * D + d];
+        T ug[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          T a = cst<T>(0.0);
+#pragma unroll
+          for (int t = 0; t < N1; ++t) a += ops.I[g][t] * sU[(e * M + c) * NP + line_node<D, N1>(n, l, t)];
+          ug[c] = a;
+        }
+        T f[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) f[c] = cst<T>(0.0);
+        if constexpr (INV) euler_flux_dot<D, T>(ug, an, mp.gamma, f);
+        if constexpr (VIS) {
+          T qg[M * D];
+#pragma unroll
+          for (int k = 0; k < M * D; ++k) {
+            T a = cst<T>(0.0);
+#pragma unroll
+            for (int t = 0; t < N1; ++t) a += ops.I[g][t] * sQ[(e * QW + k) * NP + line_node<D, N1>(n, l, t)];
+            qg[k] = a;
+          }
+          visc_flux_dot_add<D, EQ, T>(ug, qg, an, mp.gamma, mp.mu, mp.prandtl, f);
+        }
+#pragma unroll
+        for (int c = 0; c < M; ++c) sF[i * M + c] = f[c];
+      }
     }
     // face phase: point fluxes at both ends of every direction-n line
     for (int i = tid; i < ne * NL * 2; i += NT_ELEM) {
