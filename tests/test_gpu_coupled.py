@@ -47,6 +47,15 @@ def poisson_problem(name):
         pr = configs.Problem(name, mesh, EQ_POISSON, 1, 0 * u, c11_interior=1 / 20, source=f,
                              gD=fields.face_values(mesh, u))
         return pr, 1 / 20
+    if name == "hex2p2_curved_neumann":
+        base = hex_mesh(2, 2, length=1.0, periodic=False, amp=0.05)
+        u, f, g = fields.poisson_polynomial_3d(base, degs=(2, 1, 2))
+        mesh = with_boundary_kinds(base, {1: BC_NEUMANN, 3: BC_NEUMANN, 5: BC_NEUMANN})
+        # the axis-normal gradient as Neumann data (not the exact flux on curved faces; both sides
+        # solve the same discrete problem)
+        pr = configs.Problem(name, mesh, EQ_POISSON, 1, 0 * u, c11_interior=1 / 20, source=f,
+                             gD=fields.face_values(mesh, u), gN=-fields.axis_normal_face_values(mesh, g))
+        return pr, 1 / 20
     if name == "quad4p3_pert_c22_0":
         pr, _ = poisson_problem("quad4p3_pert")
         pr.name = name
@@ -86,7 +95,8 @@ def gpu_coupled(pr, c22, rtol, kind=None):
 
 
 @pytest.mark.parametrize("name,kind", [("quad4p3_pert", None), ("quad4p2_pert_neumann", None),
-                                       ("hex2p2_curved", None), ("quad4p3_pert_c22_0", None),
+                                       ("hex2p2_curved", None), ("hex2p2_curved_neumann", None),
+                                       ("quad4p3_pert_c22_0", None),
                                        ("quad4p3_pert", LDG_PRECOND_BLOCK_LU)])
 def test_coupled_solve_matches_oracle(name, kind):
     print(f"[gpu] coupled solve {name} precond {kind}", flush=True)
